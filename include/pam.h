@@ -1,0 +1,170 @@
+/*
+ * pam.h - C-ABI of the MI355X (gfx950) AS-TAX passive-acoustic-mapping library.
+ *
+ * The library reconstructs passive acoustic maps from channel RF with the
+ * cross-correlated angular-spectrum method with triple apodization (AS-TAX):
+ *   1. Fourier transform of every channel over time, keeping the bins of the
+ *      selected frequency set Omega (Eq. 1, F_t; Omega of Eq. 3);
+ *   2. per bin, the lateral Fourier transform of each apodized sub-aperture
+ *      (Eq. 1, F_x; Pattern-m apodization of Sections II-A and II-C);
+ *   3. the angular-spectrum propagator exp(i z sqrt(w^2/c^2 - kx^2)) at every
+ *      depth of the image grid (Eq. 2);
+ *   4. the inverse lateral transform giving the monochromatic fields p_i(r, w);
+ *   5. the sums over w of the sub-aperture cross-spectra, giving the NCCs
+ *      rho_12, rho_23, rho_31 (Eq. 4, negative frequencies as conjugates per
+ *      Appendix A) and the energy sum_w |p_1 + p_2 + p_3|^2;
+ *   6. the TAX weight (rho_12 rho_23 rho_31)^(1/3) (Eq. 10) with every pair
+ *      floored at eps (text after Eq. 4), normalised to maximum 1 (NNCC), and
+ *      the image I = rho_n^2 * sum_w |p_1 + p_2 + p_3|^2 (Eq. 11).
+ * With n_sub = 2 the same path computes AS-DAX (Eq. 5) and with n_sub = 1
+ * plain AS (Eq. 3, weight 1).
+ *
+ * Conventions
+ *   Units are SI.  Geometry: a linear array on the plane z = 0 whose centre is
+ *   the lateral origin (Fig. 1).  The forward time transform uses exp(-i w t),
+ *   the lateral transforms exp(-i kx x) forward and exp(+i kx x)/N_x inverse,
+ *   and the propagator exp(+i z kz) with the principal square root (evanescent
+ *   components decay as exp(-z sqrt(kx^2 - k^2)) unless PAM_EVAN_ZERO).
+ *   Bins: 0 < k < n_t/2 with lo <= k fs / n_t <= hi for some closed band.
+ *   Energies use the positive bins only, with no 1/n_t factor.
+ *
+ * Ownership and errors
+ *   The caller owns every buffer passed in; a plan owns only its resident
+ *   device tables.  pam_as_tax never allocates device memory: all scratch
+ *   space is the caller's workspace.  Every argument is validated before any
+ *   work is enqueued; on error nothing is enqueued and no output is written.
+ *   Device faults surface at the caller's next synchronisation of the stream.
+ *   A plan is immutable after creation: concurrent pam_as_tax calls on one
+ *   plan are safe when they use different streams and different workspaces.
+ */
+#ifndef PAM_H
+#define PAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pam_plan_s* pam_plan_t;
+
+typedef enum {
+  PAM_OK = 0,
+  PAM_ERR_INVALID_ARG = -1, /* a parameter is out of range, null or not finite */
+  PAM_ERR_OOM = -2,         /* device or host allocation failed (pam_plan only) */
+  PAM_ERR_DEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+  PAM_ERR_UNSUPPORTED = -4, /* valid but outside what the kernels handle (sizes) */
+  PAM_ERR_WORKSPACE = -5    /* workspace null or smaller than pam_workspace_size */
+} pam_status_t;
+
+/* How the L physical channels are laid on the N_x-column lateral grid. */
+typedef enum {
+  PAM_LATERAL_PAD = 0,  /* column o + l, o = floor((N_x - L)/2), spacing = pitch          */
+  PAM_LATERAL_STUFF = 1 /* column s*l, s = N_x / L integer, spacing = pitch / s;
+                           the zero channels in between are the paper's 2x zero-stuffing
+                           (Section II-E), apodization indexed on physical elements     */
+} pam_lateral_t;
+
+/* Arithmetic of the inverse lateral transform (the dominant contraction).  The
+ * propagator phase z*kz and its reduction modulo 2 pi are FP64 in every mode,
+ * the sine/cosine FP32; all accumulations are FP32; NCC denominators FP64. */
+typedef enum {
+  PAM_PREC_FP32 = 0,       /* FP32 operands, FP32 matrix-core products                */
+  PAM_PREC_SPLIT_BF16 = 1, /* operands split hi+lo in BF16, three BF16 products       */
+  PAM_PREC_SPLIT_FP16 = 2, /* operands split hi+lo in FP16 (power-of-two pre-scaled)  */
+  PAM_PREC_BF16 = 3,       /* single BF16 product                                     */
+  PAM_PREC_FP16 = 4        /* single FP16 product (pre-scaled)                        */
+} pam_precision_t;
+
+typedef enum {
+  PAM_EVAN_DECAY = 0, /* literal Eq. 2 with the principal root: evanescent terms decay */
+  PAM_EVAN_ZERO = 1   /* evanescent lateral wavenumbers dropped                        */
+} pam_evanescent_t;
+
+/* Imaging set-up (the paper's problem statement: RF on the array plane, element
+ * pitch and sampling rate of Section II-D, sound speed of Eq. 2, frequency set
+ * of Section II-E, image grid, apodization set of Sections II-A/II-C, eps of
+ * the text after Eq. 4).  Arrays are host memory, read during pam_plan only. */
+typedef struct {
+  int32_t n_elements;        /* L >= 1 physical channels                                  */
+  double pitch_m;            /* element pitch > 0                                         */
+  double fs_hz;              /* sampling rate > 0                                         */
+  double c_mps;              /* sound speed > 0                                           */
+  int32_t n_samples;         /* largest record length n_t served: power of two, 32..16384 */
+  int32_t n_bands;           /* >= 1 closed bands making up Omega                         */
+  const double* band_lo_hz;  /* [n_bands]                                                 */
+  const double* band_hi_hz;  /* [n_bands], lo <= hi                                       */
+  int32_t n_depths;          /* n_z >= 1                                                  */
+  const double* depths_m;    /* [n_z], finite, >= 0, measured from the array plane        */
+  int32_t n_x;               /* N_x lateral columns: multiple of 32, >= L, <= 1024        */
+  pam_lateral_t lateral;
+  int32_t n_sub;             /* 1 (AS), 2 (AS-DAX) or 3 (AS-TAX)                          */
+  const uint8_t* apod;       /* [n_sub][L] masks in {0,1}, or NULL for Pattern-m          */
+  int32_t pattern_m;         /* m of Pattern-m when apod is NULL (0 means 16)             */
+  double eps;                /* NCC floor, 0 < eps < 1 (0 means 1e-3)                     */
+  pam_precision_t precision;
+  pam_evanescent_t evanescent;
+} pam_geometry_t;
+
+/* Sizes a plan settles on, for callers that size their own buffers. */
+typedef struct {
+  int32_t n_bins;      /* bins of Omega on the plan's n_samples grid                        */
+  int32_t n_z, n_x, n_sub, n_elements, n_samples, n_pairs;
+  int32_t device;
+} pam_plan_info_t;
+
+/* Where each stage's result lies inside a workspace (byte offsets), for callers
+ * that check intermediate results.  Layouts (all row-major, last index fastest):
+ *   spectra  complex64 [F][n_sel][L]          time-transform bins, Omega order
+ *   coeffs   complex64 [F][n_sel][n_sub][N_x] folded lateral coefficients, scaled
+ *   scales   float32   [F][n_sel]             1 / (power-of-two scale of coeffs)
+ *   accum    float32   [n_split][F][n_acc][n_z][N_x] partial sums over disjoint bin
+ *            ranges; channels S_1..S_nsub then C_12, C_23, C_31 (n_sub = 3) or C_12
+ *   energy   float32   [F][n_z][N_x]          sum_w |sum_i p_i|^2
+ *   weight   float32   [F][n_z][N_x]          weight before normalisation
+ * n_sel is the number of plan bins on the call's record-length grid. */
+typedef struct {
+  size_t spectra, coeffs, scales, accum, energy, weight, blockmax, total;
+  int32_t n_sel, n_split, n_acc;
+} pam_workspace_layout_t;
+
+/* Build a plan on HIP device `device`: validates g, builds the FP64 frequency,
+ * wavenumber and depth tables, masks, lateral placement and transform tables,
+ * and copies them to the device (the paper's pre-run, Section II-E).
+ * On error *out is set to NULL and nothing is leaked. */
+pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out);
+
+pam_status_t pam_plan_get_info(pam_plan_t p, pam_plan_info_t* info);
+
+/* Copy the plan's bin indices k (on its n_samples grid) into host array bins[n_bins]. */
+pam_status_t pam_plan_get_bins(pam_plan_t p, int32_t* bins, int32_t capacity);
+
+/* Workspace bytes and stage layout for n_frames frames of n_t samples each.
+ * n_t must be n_samples / 2^j (j >= 0) and >= 32; such a record uses the plan
+ * bins whose frequency lies on its own grid (every 2^j-th bin k). */
+pam_status_t pam_workspace_size(pam_plan_t p, int64_t n_frames, int32_t n_t, size_t* bytes);
+pam_status_t pam_workspace_layout(pam_plan_t p, int64_t n_frames, int32_t n_t,
+                                  pam_workspace_layout_t* layout);
+
+/* Reconstruct n_frames frames (asynchronous on hip_stream; NULL = default stream).
+ *   rf        device float32 [n_frames][L][n_t], time fastest               (in)
+ *   image     device float32 [n_frames][n_z][N_x], I of Eq. 11              (out, required)
+ *   nncc      device float32 [n_frames][n_z][N_x], rho_n, or NULL           (out)
+ *   rho_pairs device float32 [n_frames][n_pairs][n_z][N_x], NCC of each pair
+ *             (12, 23, 31) before the eps floor, or NULL                    (out)
+ *   workspace device scratch of at least pam_workspace_size bytes, 256-byte aligned
+ * n_frames may be 0 (nothing is enqueued). */
+pam_status_t pam_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t,
+                        float* image, float* nncc, float* rho_pairs,
+                        void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Release the plan's device tables.  NULL-safe; no work may be in flight. */
+void pam_destroy(pam_plan_t p);
+
+const char* pam_status_string(pam_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAM_H */

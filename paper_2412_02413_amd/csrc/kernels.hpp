@@ -1,0 +1,425 @@
+// Device kernels of the AS-TAX hot path for gfx950 (CDNA4, wave64).
+//
+//   k1_time_fft   F_t of every channel (Eq. 1): real FFT of n_t samples as an
+//                 n_t/2-point complex radix-2 FFT in LDS, then the in-band bins.
+//   k2_lateral    apodization (Pattern-m masks) + lateral DFT F_x (Eq. 1) per
+//                 (frame, bin), folded into the coefficients of a real DFT basis.
+//   k3_fields     the propagator exp(i z kz) of Eq. 2 (FP64 phase, FP32 sin/cos)
+//                 times the folded coefficients, the inverse lateral transform as
+//                 a GEMM against a fixed real cos/sin basis on the matrix cores,
+//                 and the sums over frequency of |p_i|^2 and Re(p_i^* p_j)
+//                 (Eq. 4, Eq. 11) kept in registers.  Fields are never stored.
+//   k4_weight     NCC pairs, eps floor, TAX cube root (Eq. 10), energy, per-block max.
+//   k4_image      NNCC normalisation and I = rho_n^2 E (Eq. 11).
+//
+// Folding.  The propagator depends on kx only through kx^2, so H(q) = H(N-q) on
+// the DFT grid.  Pairing q with N-q turns the inverse transform
+//     p(x) = (1/N) sum_q H(q) P(q) e^{+2 pi i q x / N}
+// into a sum over N real basis functions, cos(2 pi q x/N) for q = 0..N/2 and
+// sin(2 pi q x/N) for q = 1..N/2-1, with complex coefficients
+//     cos q:  H(q) (P(q) + P(N-q)) / N     (P(0)/N, P(N/2)/N at the ends)
+//     sin q:  H(q) i (P(q) - P(N-q)) / N
+// so each field is a complex-by-real product with K = N: half the work of the
+// complex DFT and a basis matrix that is the same for every frame and bin.
+// Slot order: slot 2q holds "cos q", slot 2q+1 holds "sin q" (slot 1 = cos N/2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pam {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+constexpr double kTwoPiHi = 6.283185307179586232;      // 2 pi rounded to FP64
+constexpr double kTwoPiLo = 2.4492935982947064e-16;    // 2 pi - kTwoPiHi
+constexpr double kInvTwoPi = 0.15915494309189533577;
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// exp(i z kz) for one (depth, lateral wavenumber).  kzs >= 0 is a propagating
+// kz; kzs < 0 encodes an evanescent component decaying at rate -kzs.  The phase
+// z*kz is formed and reduced modulo 2 pi in FP64 (|z kz| reaches thousands of
+// radians), then the sine and cosine of the reduced angle are taken in FP32.
+__device__ __forceinline__ float2 propagator(double z, double kzs, int zero_evanescent) {
+  if (kzs >= 0.0) {
+    const double ph = z * kzs;
+    const double n = rint(ph * kInvTwoPi);
+    double r = fma(-n, kTwoPiHi, ph);
+    r = fma(-n, kTwoPiLo, r);
+    float s, c;
+    sincosf((float)r, &s, &c);
+    return make_float2(c, s);
+  }
+  if (zero_evanescent) return make_float2(0.f, 0.f);
+  return make_float2(expf((float)(z * kzs)), 0.f);
+}
+
+// --------------------------------------------------------------------------
+// K1: time FFT.  One workgroup per (channel, frame).  x[2n] + i x[2n+1] is
+// transformed as an M = n_t/2 point complex FFT (bit-reversed load, in-place
+// radix-2 decimation in time in LDS), then X[k] = E[k] + e^{-2 pi i k/n_t} O[k]
+// with E/O the transforms of the even/odd samples recovered from Z[k], Z[M-k].
+// --------------------------------------------------------------------------
+struct K1Args {
+  const float* rf;        // [F][L][n_t]
+  float2* spectra;        // [F][n_sel][L]
+  const float2* tw;       // e^{-2 pi i m / n_tp}, m < n_tp/2 (plan grid)
+  const int32_t* ksel;    // bin k on the call's grid, [n_sel]
+  int32_t L, n_t, log2m, tw_stride, n_sel;
+};
+
+__global__ __launch_bounds__(256) void k1_time_fft(K1Args a) {
+  extern __shared__ float2 z[];  // [M]
+  const int l = blockIdx.x, f = blockIdx.y;
+  const int M = a.n_t >> 1;
+  const float2* src = reinterpret_cast<const float2*>(a.rf + ((size_t)f * a.L + l) * a.n_t);
+  for (int n = threadIdx.x; n < M; n += blockDim.x) {
+    const unsigned r = __brev((unsigned)n) >> (32 - a.log2m);
+    z[r] = src[n];
+  }
+  __syncthreads();
+  for (int half = 1; half < M; half <<= 1) {
+    // twiddle e^{-2 pi i pos / (2 half)} = tw[pos * (n_t / (2 half)) * tw_stride]
+    const int step = (a.n_t / (2 * half)) * a.tw_stride;
+    for (int bf = threadIdx.x; bf < (M >> 1); bf += blockDim.x) {
+      const int pos = bf & (half - 1);
+      const int i0 = ((bf - pos) << 1) + pos;
+      const int i1 = i0 + half;
+      const float2 w = a.tw[pos * step];
+      const float2 u = z[i0];
+      const float2 v = cmul(z[i1], w);
+      z[i0] = cadd(u, v);
+      z[i1] = csub(u, v);
+    }
+    __syncthreads();
+  }
+  float2* dst = a.spectra + (size_t)f * a.n_sel * a.L + l;
+  for (int b = threadIdx.x; b < a.n_sel; b += blockDim.x) {
+    const int k = a.ksel[b];               // 0 < k < M
+    const float2 zk = z[k];
+    const float2 zc = make_float2(z[M - k].x, -z[M - k].y);
+    const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+    const float2 d = csub(zk, zc);
+    const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // (zk - zc) / (2i)
+    const float2 w = a.tw[k * a.tw_stride];                   // e^{-2 pi i k / n_t}
+    dst[(size_t)b * a.L] = cadd(e, cmul(w, o));
+  }
+}
+
+// --------------------------------------------------------------------------
+// K2: apodize, place on the lateral grid, lateral DFT, fold into slot order and
+// scale by a power of two (exact) so that the largest coefficient lies in
+// [2^11, 2^12): this keeps FP16 hi/lo splits of the products normal and is a
+// no-op on the results.  One workgroup per (bin, frame).
+// --------------------------------------------------------------------------
+struct K2Args {
+  const float2* spectra;  // [F][n_sel][L]
+  float2* coeffs;         // [F][n_sel][n_sub][N]
+  float* inv_scale;       // [F][n_sel]
+  const float2* twx;      // e^{-2 pi i m / N}, m < N
+  const float* masks;     // [n_sub][L]
+  const int32_t* cols;    // [L] grid column of each element
+  int32_t L, N, n_sub, n_sel;
+};
+
+__global__ __launch_bounds__(256) void k2_lateral(K2Args a) {
+  extern __shared__ float2 sm2[];
+  const int N = a.N;
+  float2* u = sm2;                    // [L]
+  float2* P = sm2 + a.L;              // [n_sub][N] lateral spectra
+  float2* Gf = P + a.n_sub * N;       // [n_sub][N] folded coefficients
+  __shared__ float red[256];
+  const int b = blockIdx.x, f = blockIdx.y;
+  const size_t fb = (size_t)f * a.n_sel + b;
+  for (int l = threadIdx.x; l < a.L; l += blockDim.x) u[l] = a.spectra[fb * a.L + l];
+  __syncthreads();
+  for (int q = threadIdx.x; q < N; q += blockDim.x) {
+    float2 acc[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    for (int l = 0; l < a.L; ++l) {
+      const int m = (int)(((long long)q * a.cols[l]) % N);
+      const float2 t = cmul(u[l], a.twx[m]);
+      for (int i = 0; i < a.n_sub; ++i) {
+        const float mk = a.masks[i * a.L + l];
+        acc[i].x = fmaf(mk, t.x, acc[i].x);
+        acc[i].y = fmaf(mk, t.y, acc[i].y);
+      }
+    }
+    for (int i = 0; i < a.n_sub; ++i) P[i * N + q] = acc[i];
+  }
+  __syncthreads();
+  // fold into slot order and find the largest magnitude component
+  const float invN = 1.0f / (float)N;
+  float mx = 0.f;
+  for (int e = threadIdx.x; e < a.n_sub * N; e += blockDim.x) {
+    const int i = e / N, s = e - i * N, q = s >> 1;
+    const float2* Pi = P + i * N;
+    float2 g;
+    if ((s & 1) == 0) {
+      g = (q == 0) ? Pi[0] : cadd(Pi[q], Pi[N - q]);
+    } else if (q == 0) {
+      g = Pi[N / 2];
+    } else {
+      const float2 d = csub(Pi[q], Pi[N - q]);
+      g = make_float2(-d.y, d.x);  // i (P(q) - P(N-q))
+    }
+    g.x *= invN;
+    g.y *= invN;
+    mx = fmaxf(mx, fmaxf(fabsf(g.x), fabsf(g.y)));
+    Gf[e] = g;
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  const float gmax = red[0];
+  int ex = 0;
+  frexpf(gmax, &ex);  // gmax = m 2^ex, m in [0.5, 1)
+  const float scale = (gmax > 0.f) ? ldexpf(1.0f, 12 - ex) : 1.0f;
+  float2* dst = a.coeffs + fb * a.n_sub * N;
+  for (int e = threadIdx.x; e < a.n_sub * N; e += blockDim.x) {
+    const float2 g = Gf[e];
+    dst[e] = make_float2(g.x * scale, g.y * scale);
+  }
+  if (threadIdx.x == 0) a.inv_scale[fb] = 1.0f / scale;
+}
+
+// --------------------------------------------------------------------------
+// K3: fused propagate + inverse lateral transform + cross-spectra over bins.
+//
+// GEMM view for one (frame, bin): rows = depths, K = N slots, columns = x.
+//   A_t[d, s] = Re or Im of H(d, q(s)) * coeff_i[s]   (t = 2 i + {0: re, 1: im})
+//   B[s, x]   = basis (cos / sin), fixed
+//   p_i(d, x) = (A_{2i} B)(d, x) + i (A_{2i+1} B)(d, x)
+// A workgroup owns a 32-depth tile and NW 32-column x tiles (one per wave) of one
+// frame, and a contiguous range of bins.  Per bin it stages the frame's
+// coefficients in LDS, generates A chunk by chunk in LDS (each (d, q) phase once,
+// shared by all sub-apertures, both slots and all waves), and each wave runs
+// 2*NSUB 32x32 FP32 matrix-core tiles over K with B read from the L2-resident
+// basis.  The finished fields of the bin are folded into six per-pixel register
+// accumulators and discarded.
+// --------------------------------------------------------------------------
+struct K3Args {
+  const float2* coeffs;    // [F][n_sel][n_sub][N] slot order
+  const float* inv_scale;  // [F][n_sel]
+  const double* kz;        // [n_bins_plan][N/2 + 1] signed kz
+  const double* z;         // [n_z]
+  const int32_t* sel;      // [n_sel] plan bin index of each selected bin
+  const float* basis;      // [N][N] slot-major fixed real basis
+  float* accum;            // [n_split][F][n_acc][n_z][N]
+  int32_t N, n_z, n_sel, F, n_dt, n_xg, n_split, bins_per_split, zero_evanescent;
+};
+
+template <int NSUB>
+struct AccCount {
+  static constexpr int pairs = NSUB == 3 ? 3 : (NSUB == 2 ? 1 : 0);
+  static constexpr int total = NSUB + pairs;
+};
+
+template <int NSUB, int NW, int KC>
+__global__ __launch_bounds__(NW * 64, 1) void k3_fields_fp32(K3Args a) {
+  constexpr int NT = 2 * NSUB;
+  constexpr int NP = AccCount<NSUB>::pairs;
+  // KC: slots per LDS chunk
+  extern __shared__ float smem[];
+  float* As = smem;                                         // [NT][KC][32]
+  float2* Gs = reinterpret_cast<float2*>(smem + NT * KC * 32);  // [NSUB][N]
+
+  const int N = a.N;
+  const int HQ = N / 2 + 1;
+  int bid = blockIdx.x;
+  const int sp = bid % a.n_split; bid /= a.n_split;
+  const int xg = bid % a.n_xg;    bid /= a.n_xg;
+  const int dt = bid % a.n_dt;    bid /= a.n_dt;
+  const int f = bid;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int x0 = (xg * NW + w) * 32;
+  const int d0 = dt * 32;
+  const int b_begin = sp * a.bins_per_split;
+  const int b_end = min(a.n_sel, b_begin + a.bins_per_split);
+  const int half = lane >> 5, col = lane & 31;
+
+  float accS[NSUB][16];
+  float accC[NP > 0 ? NP : 1][16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) accS[i][v] = 0.f;
+#pragma unroll
+    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
+  }
+
+  for (int b = b_begin; b < b_end; ++b) {
+    const size_t fb = (size_t)f * a.n_sel + b;
+    const float2* gsrc = a.coeffs + fb * NSUB * N;
+    for (int e = tid; e < NSUB * N; e += NW * 64) Gs[e] = gsrc[e];
+    const float inv = a.inv_scale[fb];
+    const double* kzb = a.kz + (size_t)a.sel[b] * HQ;
+    __syncthreads();
+
+    v16f C[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) C[t][v] = 0.f;
+
+    for (int c0 = 0; c0 < N; c0 += KC) {
+      // A chunk: slots c0 .. c0+KC-1  <->  q = c0/2 .. c0/2 + KC/2 - 1
+      for (int e = tid; e < 32 * (KC / 2); e += NW * 64) {
+        const int r = e & 31, ql = e >> 5;
+        const int q = (c0 >> 1) + ql;
+        const int d = d0 + r;
+        float2 h0 = make_float2(0.f, 0.f), h1 = h0;
+        if (d < a.n_z) {
+          const double zd = a.z[d];
+          h0 = propagator(zd, kzb[q], a.zero_evanescent);
+          h1 = (q == 0) ? propagator(zd, kzb[N / 2], a.zero_evanescent) : h0;
+        }
+#pragma unroll
+        for (int i = 0; i < NSUB; ++i) {
+          const float2 a0 = cmul(h0, Gs[i * N + 2 * q]);
+          const float2 a1 = cmul(h1, Gs[i * N + 2 * q + 1]);
+          As[((2 * i + 0) * KC + 2 * ql + 0) * 32 + r] = a0.x;
+          As[((2 * i + 1) * KC + 2 * ql + 0) * 32 + r] = a0.y;
+          As[((2 * i + 0) * KC + 2 * ql + 1) * 32 + r] = a1.x;
+          As[((2 * i + 1) * KC + 2 * ql + 1) * 32 + r] = a1.y;
+        }
+      }
+      __syncthreads();
+      const float* bp = a.basis + (size_t)(c0 + half) * N + x0 + col;
+#pragma unroll 4
+      for (int j = 0; j < KC / 2; ++j) {
+        const float bv = bp[(size_t)(2 * j) * N];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float av = As[(t * KC + 2 * j + half) * 32 + col];
+          C[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, C[t], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+    }
+    // fold this bin's fields into the per-pixel sums
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float pr[NSUB], pim[NSUB];
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) {
+        pr[i] = C[2 * i][v] * inv;
+        pim[i] = C[2 * i + 1][v] * inv;
+        accS[i][v] = fmaf(pr[i], pr[i], fmaf(pim[i], pim[i], accS[i][v]));
+      }
+      if constexpr (NSUB == 3) {
+        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
+        accC[1][v] = fmaf(pr[1], pr[2], fmaf(pim[1], pim[2], accC[1][v]));
+        accC[2][v] = fmaf(pr[2], pr[0], fmaf(pim[2], pim[0], accC[2][v]));
+      } else if constexpr (NSUB == 2) {
+        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
+      }
+    }
+  }
+  // 32x32 accumulator layout: lane holds column (lane & 31) and rows
+  // 8*(v/4) + 4*(lane/32) + v%4 for v = 0..15.
+  constexpr int NA = AccCount<NSUB>::total;
+  const size_t plane = (size_t)a.n_z * N;
+  float* dst = a.accum + ((size_t)sp * a.F + f) * NA * plane;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int row = d0 + 8 * (v >> 2) + 4 * half + (v & 3);
+    if (row < a.n_z) {
+      const size_t o = (size_t)row * N + x0 + col;
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) dst[i * plane + o] = accS[i][v];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) dst[(NSUB + p) * plane + o] = accC[p][v];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// K4: NCC, weight, energy, NNCC and image.
+// --------------------------------------------------------------------------
+struct K4Args {
+  const float* accum;   // [n_split][F][n_acc][n_z][N]
+  float* energy;        // [F][pix]
+  float* weight;        // [F][pix]
+  float* blockmax;      // [F][n_blk]
+  float* rho_pairs;     // [F][n_pairs][pix] or null
+  float* image;         // [F][pix]
+  float* nncc;          // [F][pix] or null
+  int32_t pix, F, n_split, n_sub, n_blk;
+  double eps;
+};
+
+__global__ __launch_bounds__(256) void k4_weight(K4Args a) {
+  __shared__ float red[256];
+  const int f = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int na = a.n_sub == 3 ? 6 : (a.n_sub == 2 ? 3 : 1);
+  float wv = 0.f;
+  if (p < a.pix) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < a.n_split; ++s) {
+      const float* src = a.accum + ((size_t)s * a.F + f) * na * a.pix + p;
+      for (int c = 0; c < na; ++c) v[c] += (double)src[(size_t)c * a.pix];
+    }
+    double E, w;
+    if (a.n_sub == 1) {
+      E = v[0];
+      w = 1.0;
+    } else {
+      const int np = a.n_sub == 3 ? 3 : 1;
+      const int pi_[3] = {0, 1, 2}, pj_[3] = {1, 2, 0};
+      double prod = 1.0, esum = 0.0;
+      for (int i = 0; i < a.n_sub; ++i) esum += v[i];
+      for (int q = 0; q < np; ++q) {
+        const double cc = v[a.n_sub + q];
+        esum += 2.0 * cc;
+        const double den = sqrt(v[pi_[q]]) * sqrt(v[pj_[q]]);
+        const double r = den > 0.0 ? cc / den : 0.0;
+        if (a.rho_pairs) a.rho_pairs[((size_t)f * np + q) * a.pix + p] = (float)r;
+        prod *= fmin(1.0, fmax(a.eps, r));
+      }
+      E = esum;
+      w = (a.n_sub == 3) ? cbrt(prod) : prod;
+    }
+    a.energy[(size_t)f * a.pix + p] = (float)E;
+    a.weight[(size_t)f * a.pix + p] = (float)w;
+    wv = (float)w;
+  }
+  red[threadIdx.x] = wv;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.blockmax[(size_t)f * a.n_blk + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k4_image(K4Args a) {
+  __shared__ float red[256];
+  const int f = blockIdx.y;
+  float m = 0.f;
+  for (int i = threadIdx.x; i < a.n_blk; i += 256) m = fmaxf(m, a.blockmax[(size_t)f * a.n_blk + i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  const float mx = red[0];
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < a.pix) {
+    const size_t o = (size_t)f * a.pix + p;
+    const float rn = a.weight[o] / mx;
+    a.image[o] = rn * rn * a.energy[o];
+    if (a.nncc) a.nncc[o] = rn;
+  }
+}
+
+}  // namespace pam

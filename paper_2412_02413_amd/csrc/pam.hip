@@ -1,0 +1,460 @@
+// Host side of the AS-TAX library: plan (the paper's pre-run, Section II-E),
+// validation, workspace layout and kernel launches behind the C-ABI of pam.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pam.h"
+#include "kernels.hpp"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMinSamples = 32;
+constexpr int kMaxSamples = 16384;
+constexpr int kMaxNx = 1024;
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (ok && hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// One bin subset per record length n_samples / 2^j.
+struct Level {
+  int n_t = 0;
+  int stride = 1;        // 2^j
+  int n_sel = 0;
+  int32_t* d_sel = nullptr;   // plan bin index of each selected bin
+  int32_t* d_ksel = nullptr;  // bin k on the level's own grid
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct pam_plan_s {
+  int device = 0;
+  int L = 0, n_t = 0, N = 0, n_z = 0, n_sub = 0, n_bins = 0;
+  double eps = 1e-3;
+  int precision = 0, zero_evanescent = 0;
+  std::vector<int32_t> bins;  // k on the plan grid
+  std::vector<Level> levels;
+  // device tables
+  double* d_kz = nullptr;      // [n_bins][N/2+1] signed kz
+  double* d_z = nullptr;       // [n_z]
+  float2* d_tw = nullptr;      // [n_t/2] time-FFT twiddles
+  float2* d_twx = nullptr;     // [N] lateral DFT twiddles
+  float* d_masks = nullptr;    // [n_sub][L]
+  int32_t* d_cols = nullptr;   // [L]
+  float* d_basis = nullptr;    // [N][N] slot-major cos/sin basis
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+void free_plan(pam_plan_s* p) {
+  if (!p) return;
+  for (void* q : p->allocs) (void)hipFree(q);
+  delete p;
+}
+
+template <typename T>
+pam_status_t upload(pam_plan_s* p, T** dst, const T* src, size_t n) {
+  void* ptr = nullptr;
+  const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  if (hipMalloc(&ptr, bytes) != hipSuccess) return PAM_ERR_OOM;
+  p->allocs.push_back(ptr);
+  if (n && hipMemcpy(ptr, src, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return PAM_ERR_DEVICE;
+  *dst = static_cast<T*>(ptr);
+  return PAM_OK;
+}
+
+pam_status_t validate(const pam_geometry_t* g) {
+  if (!g) return PAM_ERR_INVALID_ARG;
+  if (g->n_elements < 1 || !finite_pos(g->pitch_m) || !finite_pos(g->fs_hz) || !finite_pos(g->c_mps))
+    return PAM_ERR_INVALID_ARG;
+  if (g->n_samples < 2) return PAM_ERR_INVALID_ARG;
+  if (!is_pow2(g->n_samples) || g->n_samples < kMinSamples || g->n_samples > kMaxSamples)
+    return PAM_ERR_UNSUPPORTED;
+  if (g->n_bands < 1 || !g->band_lo_hz || !g->band_hi_hz) return PAM_ERR_INVALID_ARG;
+  for (int b = 0; b < g->n_bands; ++b) {
+    const double lo = g->band_lo_hz[b], hi = g->band_hi_hz[b];
+    if (!std::isfinite(lo) || !std::isfinite(hi) || lo < 0.0 || hi < lo) return PAM_ERR_INVALID_ARG;
+  }
+  if (g->n_depths < 1 || !g->depths_m) return PAM_ERR_INVALID_ARG;
+  for (int d = 0; d < g->n_depths; ++d)
+    if (!std::isfinite(g->depths_m[d]) || g->depths_m[d] < 0.0) return PAM_ERR_INVALID_ARG;
+  if (g->n_x < g->n_elements || g->n_x < 2) return PAM_ERR_INVALID_ARG;
+  if (g->n_x % 32 != 0 || g->n_x > kMaxNx) return PAM_ERR_UNSUPPORTED;
+  if (g->lateral != PAM_LATERAL_PAD && g->lateral != PAM_LATERAL_STUFF) return PAM_ERR_INVALID_ARG;
+  if (g->lateral == PAM_LATERAL_STUFF && g->n_x % g->n_elements != 0) return PAM_ERR_INVALID_ARG;
+  if (g->n_sub < 1 || g->n_sub > 3) return PAM_ERR_INVALID_ARG;
+  if (g->apod) {
+    for (int i = 0; i < g->n_sub * g->n_elements; ++i)
+      if (g->apod[i] > 1) return PAM_ERR_INVALID_ARG;
+  } else if (g->pattern_m < 0) {
+    return PAM_ERR_INVALID_ARG;
+  }
+  if (!(g->eps >= 0.0 && g->eps < 1.0)) return PAM_ERR_INVALID_ARG;
+  if (g->precision < PAM_PREC_FP32 || g->precision > PAM_PREC_FP16) return PAM_ERR_INVALID_ARG;
+  if (g->precision != PAM_PREC_FP32) return PAM_ERR_UNSUPPORTED;
+  if (g->evanescent != PAM_EVAN_DECAY && g->evanescent != PAM_EVAN_ZERO) return PAM_ERR_INVALID_ARG;
+  return PAM_OK;
+}
+
+// bins 0 < k < n_t/2 whose frequency k*fs/n_t lies in a closed band
+std::vector<int32_t> select_bins(const pam_geometry_t* g) {
+  std::vector<int32_t> ks;
+  for (int k = 1; k < (g->n_samples + 1) / 2; ++k) {
+    const double f = ((double)k * g->fs_hz) / (double)g->n_samples;
+    for (int b = 0; b < g->n_bands; ++b) {
+      if (g->band_lo_hz[b] <= f && f <= g->band_hi_hz[b]) {
+        ks.push_back(k);
+        break;
+      }
+    }
+  }
+  return ks;
+}
+
+int waves_for(int N) {
+  const int tiles = N / 32;
+  for (int nw : {8, 4, 2, 1})
+    if (tiles % nw == 0) return nw;
+  return 1;
+}
+
+struct LaunchShape {
+  int n_dt, nw, n_xg, n_split, bins_per_split, kc;
+};
+
+LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
+  LaunchShape s;
+  s.n_dt = (p->n_z + 31) / 32;
+  s.nw = waves_for(p->N);
+  s.n_xg = p->N / (32 * s.nw);
+  s.kc = (p->N > 512) ? 32 : 64;
+  const int64_t base = F * s.n_dt * s.n_xg;
+  int split = 1;
+  if (base > 0 && base < 512) {
+    split = (int)((512 + base - 1) / base);
+    split = std::min(split, std::max(1, n_sel / 8));
+  }
+  split = std::max(1, std::min(split, std::max(1, n_sel)));
+  s.bins_per_split = (n_sel + split - 1) / split;
+  s.n_split = (n_sel + s.bins_per_split - 1) / s.bins_per_split;
+  if (n_sel == 0) {
+    s.n_split = 1;
+    s.bins_per_split = 0;
+  }
+  return s;
+}
+
+const Level* level_for(const pam_plan_s* p, int n_t) {
+  for (const Level& lv : p->levels)
+    if (lv.n_t == n_t) return &lv;
+  return nullptr;
+}
+
+int n_acc(int n_sub) { return n_sub == 3 ? 6 : (n_sub == 2 ? 3 : 1); }
+
+pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layout_t* out) {
+  const Level* lv = level_for(p, n_t);
+  if (!lv) return PAM_ERR_INVALID_ARG;
+  const LaunchShape s = k3_shape(p, F, lv->n_sel);
+  const size_t pix = (size_t)p->n_z * p->N;
+  const size_t n_blk = (pix + 255) / 256;
+  pam_workspace_layout_t L{};
+  size_t o = 0;
+  L.spectra = o;  o = align256(o + (size_t)F * lv->n_sel * p->L * sizeof(float2));
+  L.coeffs = o;   o = align256(o + (size_t)F * lv->n_sel * p->n_sub * p->N * sizeof(float2));
+  L.scales = o;   o = align256(o + (size_t)F * lv->n_sel * sizeof(float));
+  L.accum = o;    o = align256(o + (size_t)s.n_split * F * n_acc(p->n_sub) * pix * sizeof(float));
+  L.energy = o;   o = align256(o + (size_t)F * pix * sizeof(float));
+  L.weight = o;   o = align256(o + (size_t)F * pix * sizeof(float));
+  L.blockmax = o; o = align256(o + (size_t)F * n_blk * sizeof(float));
+  L.total = std::max<size_t>(o, 256);
+  L.n_sel = lv->n_sel;
+  L.n_split = s.n_split;
+  L.n_acc = n_acc(p->n_sub);
+  *out = L;
+  return PAM_OK;
+}
+
+template <int NSUB, int NW, int KC>
+hipError_t launch_k3_t(const pam::K3Args& a, int blocks, hipStream_t st) {
+  const size_t lds = (size_t)(2 * NSUB) * KC * 32 * sizeof(float) + (size_t)NSUB * a.N * sizeof(float2);
+  hipLaunchKernelGGL((pam::k3_fields_fp32<NSUB, NW, KC>), dim3(blocks), dim3(NW * 64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int NSUB, int KC>
+hipError_t launch_k3_nw(int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
+  switch (nw) {
+    case 8: return launch_k3_t<NSUB, 8, KC>(a, blocks, st);
+    case 4: return launch_k3_t<NSUB, 4, KC>(a, blocks, st);
+    case 2: return launch_k3_t<NSUB, 2, KC>(a, blocks, st);
+    default: return launch_k3_t<NSUB, 1, KC>(a, blocks, st);
+  }
+}
+
+template <int NSUB>
+hipError_t launch_k3_kc(int kc, int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
+  return kc == 32 ? launch_k3_nw<NSUB, 32>(nw, a, blocks, st) : launch_k3_nw<NSUB, 64>(nw, a, blocks, st);
+}
+
+hipError_t launch_k3(int n_sub, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
+  switch (n_sub) {
+    case 3: return launch_k3_kc<3>(s.kc, s.nw, a, blocks, st);
+    case 2: return launch_k3_kc<2>(s.kc, s.nw, a, blocks, st);
+    default: return launch_k3_kc<1>(s.kc, s.nw, a, blocks, st);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pam_status_string(pam_status_t s) {
+  switch (s) {
+    case PAM_OK: return "ok";
+    case PAM_ERR_INVALID_ARG: return "invalid argument";
+    case PAM_ERR_OOM: return "out of memory";
+    case PAM_ERR_DEVICE: return "device error";
+    case PAM_ERR_UNSUPPORTED: return "unsupported size or mode";
+    case PAM_ERR_WORKSPACE: return "workspace missing or too small";
+  }
+  return "unknown status";
+}
+
+pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
+  if (!out) return PAM_ERR_INVALID_ARG;
+  *out = nullptr;
+  pam_status_t st = validate(g);
+  if (st != PAM_OK) return st;
+  std::vector<int32_t> ks = select_bins(g);
+  if (ks.empty()) return PAM_ERR_INVALID_ARG;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return PAM_ERR_DEVICE;
+  DeviceGuard guard(device);
+  if (!guard.ok) return PAM_ERR_DEVICE;
+
+  pam_plan_s* p = new (std::nothrow) pam_plan_s();
+  if (!p) return PAM_ERR_OOM;
+  p->device = device;
+  p->L = g->n_elements;
+  p->n_t = g->n_samples;
+  p->N = g->n_x;
+  p->n_z = g->n_depths;
+  p->n_sub = g->n_sub;
+  p->n_bins = (int)ks.size();
+  p->eps = g->eps > 0.0 ? g->eps : 1e-3;
+  p->precision = g->precision;
+  p->zero_evanescent = g->evanescent == PAM_EVAN_ZERO;
+  p->bins = ks;
+  const int L = p->L, N = p->N, HQ = N / 2 + 1;
+
+  // lateral placement: grid column of each element and grid spacing
+  std::vector<int32_t> cols(L);
+  double dx;
+  if (g->lateral == PAM_LATERAL_PAD) {
+    const int o = (N - L) / 2;
+    for (int l = 0; l < L; ++l) cols[l] = o + l;
+    dx = g->pitch_m;
+  } else {
+    const int s = N / L;
+    for (int l = 0; l < L; ++l) cols[l] = s * l;
+    dx = g->pitch_m / s;
+  }
+  // apodization masks: explicit or Pattern-m (a_i[l] = 1 iff floor(l/m) mod n == i)
+  std::vector<float> masks((size_t)p->n_sub * L, 0.f);
+  const int m = g->pattern_m > 0 ? g->pattern_m : 16;
+  for (int i = 0; i < p->n_sub; ++i)
+    for (int l = 0; l < L; ++l)
+      masks[(size_t)i * L + l] = g->apod ? (float)g->apod[(size_t)i * L + l] : (((l / m) % p->n_sub) == i ? 1.f : 0.f);
+  // signed kz for the folded half grid q = 0..N/2: kx_q = 2 pi q / (N dx)
+  std::vector<double> kz((size_t)p->n_bins * HQ);
+  for (int b = 0; b < p->n_bins; ++b) {
+    const double f = ((double)ks[b] * g->fs_hz) / (double)g->n_samples;
+    const double k = 2.0 * kPi * f / g->c_mps;
+    for (int q = 0; q < HQ; ++q) {
+      const double kx = 2.0 * kPi * (double)q / ((double)N * dx);
+      const double d = k * k - kx * kx;
+      kz[(size_t)b * HQ + q] = d >= 0.0 ? std::sqrt(d) : -std::sqrt(-d);
+    }
+  }
+  std::vector<double> z(g->depths_m, g->depths_m + p->n_z);
+  // transform tables from exact integer angles
+  std::vector<float2> tw(p->n_t / 2), twx(N);
+  for (int i = 0; i < p->n_t / 2; ++i) {
+    const double a = 2.0 * kPi * (double)i / (double)p->n_t;
+    tw[i] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  for (int i = 0; i < N; ++i) {
+    const double a = 2.0 * kPi * (double)i / (double)N;
+    twx[i] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  std::vector<float> basis((size_t)N * N);
+  for (int s = 0; s < N; ++s) {
+    const int q = s >> 1;
+    for (int x = 0; x < N; ++x) {
+      double v;
+      if ((s & 1) == 0) {
+        v = std::cos(2.0 * kPi * (double)(((long long)q * x) % N) / (double)N);
+      } else if (q == 0) {
+        v = (x & 1) ? -1.0 : 1.0;  // cos(pi x)
+      } else {
+        v = std::sin(2.0 * kPi * (double)(((long long)q * x) % N) / (double)N);
+      }
+      basis[(size_t)s * N + x] = (float)v;
+    }
+  }
+
+  do {
+    if ((st = upload(p, &p->d_kz, kz.data(), kz.size())) != PAM_OK) break;
+    if ((st = upload(p, &p->d_z, z.data(), z.size())) != PAM_OK) break;
+    if ((st = upload(p, &p->d_tw, tw.data(), tw.size())) != PAM_OK) break;
+    if ((st = upload(p, &p->d_twx, twx.data(), twx.size())) != PAM_OK) break;
+    if ((st = upload(p, &p->d_masks, masks.data(), masks.size())) != PAM_OK) break;
+    if ((st = upload(p, &p->d_cols, cols.data(), cols.size())) != PAM_OK) break;
+    if ((st = upload(p, &p->d_basis, basis.data(), basis.size())) != PAM_OK) break;
+    // bin subsets for records of n_t / 2^j samples
+    for (int stride = 1; p->n_t / stride >= kMinSamples; stride <<= 1) {
+      Level lv;
+      lv.n_t = p->n_t / stride;
+      lv.stride = stride;
+      std::vector<int32_t> sel, ksel;
+      for (int b = 0; b < p->n_bins; ++b)
+        if (ks[b] % stride == 0) {
+          sel.push_back(b);
+          ksel.push_back(ks[b] / stride);
+        }
+      lv.n_sel = (int)sel.size();
+      if ((st = upload(p, &lv.d_sel, sel.data(), sel.size())) != PAM_OK) break;
+      if ((st = upload(p, &lv.d_ksel, ksel.data(), ksel.size())) != PAM_OK) break;
+      p->levels.push_back(lv);
+    }
+  } while (false);
+  if (st != PAM_OK) {
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return PAM_OK;
+}
+
+pam_status_t pam_plan_get_info(pam_plan_t p, pam_plan_info_t* info) {
+  if (!p || !info) return PAM_ERR_INVALID_ARG;
+  info->n_bins = p->n_bins;
+  info->n_z = p->n_z;
+  info->n_x = p->N;
+  info->n_sub = p->n_sub;
+  info->n_elements = p->L;
+  info->n_samples = p->n_t;
+  info->n_pairs = p->n_sub == 3 ? 3 : (p->n_sub == 2 ? 1 : 0);
+  info->device = p->device;
+  return PAM_OK;
+}
+
+pam_status_t pam_plan_get_bins(pam_plan_t p, int32_t* bins, int32_t capacity) {
+  if (!p || !bins || capacity < p->n_bins) return PAM_ERR_INVALID_ARG;
+  std::memcpy(bins, p->bins.data(), sizeof(int32_t) * p->n_bins);
+  return PAM_OK;
+}
+
+pam_status_t pam_workspace_layout(pam_plan_t p, int64_t n_frames, int32_t n_t, pam_workspace_layout_t* out) {
+  if (!p || !out || n_frames < 0) return PAM_ERR_INVALID_ARG;
+  return layout(p, n_frames, n_t, out);
+}
+
+pam_status_t pam_workspace_size(pam_plan_t p, int64_t n_frames, int32_t n_t, size_t* bytes) {
+  if (!bytes) return PAM_ERR_INVALID_ARG;
+  pam_workspace_layout_t L;
+  pam_status_t st = pam_workspace_layout(p, n_frames, n_t, &L);
+  if (st == PAM_OK) *bytes = L.total;
+  return st;
+}
+
+pam_status_t pam_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
+                        float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!p || n_frames < 0) return PAM_ERR_INVALID_ARG;
+  if (n_frames > (int64_t)1 << 20) return PAM_ERR_UNSUPPORTED;
+  pam_workspace_layout_t W;
+  pam_status_t st = layout(p, n_frames, n_t, &W);
+  if (st != PAM_OK) return st;
+  if (n_frames == 0) return PAM_OK;
+  if (!rf || !image) return PAM_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < W.total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return PAM_ERR_WORKSPACE;
+  if (rho_pairs && p->n_sub == 1) return PAM_ERR_INVALID_ARG;
+  const Level* lv = level_for(p, n_t);
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return PAM_ERR_DEVICE;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  char* ws = static_cast<char*>(workspace);
+  float2* spectra = reinterpret_cast<float2*>(ws + W.spectra);
+  float2* coeffs = reinterpret_cast<float2*>(ws + W.coeffs);
+  float* scales = reinterpret_cast<float*>(ws + W.scales);
+  float* accum = reinterpret_cast<float*>(ws + W.accum);
+  float* energy = reinterpret_cast<float*>(ws + W.energy);
+  float* weight = reinterpret_cast<float*>(ws + W.weight);
+  float* blockmax = reinterpret_cast<float*>(ws + W.blockmax);
+  const int F = (int)n_frames;
+
+  // K1: time FFT, one workgroup per (channel, frame)
+  {
+    pam::K1Args a{rf, spectra, p->d_tw, lv->d_ksel, p->L, n_t, ilog2(n_t / 2), lv->stride, lv->n_sel};
+    hipLaunchKernelGGL(pam::k1_time_fft, dim3(p->L, F), dim3(256), (size_t)(n_t / 2) * sizeof(float2), stream, a);
+    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
+  }
+  // K2: lateral DFT + fold, one workgroup per (bin, frame)
+  {
+    pam::K2Args a{spectra, coeffs, scales, p->d_twx, p->d_masks, p->d_cols, p->L, p->N, p->n_sub, lv->n_sel};
+    const size_t lds = (size_t)(p->L + 2 * p->n_sub * p->N) * sizeof(float2);
+    hipLaunchKernelGGL(pam::k2_lateral, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
+  }
+  // K3: fused propagate / inverse lateral transform / cross-spectra
+  {
+    const LaunchShape s = k3_shape(p, F, lv->n_sel);
+    pam::K3Args a{coeffs, scales, p->d_kz, p->d_z, lv->d_sel, p->d_basis, accum,
+                  p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent};
+    const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
+    if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
+    if (launch_k3(p->n_sub, s, a, (int)blocks, stream) != hipSuccess) return PAM_ERR_DEVICE;
+  }
+  // K4: NCC / weight / energy, then NNCC and image
+  {
+    const int pix = p->n_z * p->N;
+    const int n_blk = (pix + 255) / 256;
+    pam::K4Args a{accum, energy, weight, blockmax, rho_pairs, image, nncc, pix, F, W.n_split, p->n_sub, n_blk, p->eps};
+    hipLaunchKernelGGL(pam::k4_weight, dim3(n_blk, F), dim3(256), 0, stream, a);
+    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
+    hipLaunchKernelGGL(pam::k4_image, dim3(n_blk, F), dim3(256), 0, stream, a);
+    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
+  }
+  return PAM_OK;
+}
+
+void pam_destroy(pam_plan_t p) { free_plan(p); }
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libpam (include/pam.h): argument marshalling only.
+
+Every step of the reconstruction runs in the HIP library; PyTorch supplies
+device memory and streams.  The library must be built (``build.py`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpam.so")
+
+PAM_OK, PAM_ERR_INVALID_ARG, PAM_ERR_OOM, PAM_ERR_DEVICE, PAM_ERR_UNSUPPORTED, PAM_ERR_WORKSPACE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp32": 0, "split_bf16": 1, "split_fp16": 2, "bf16": 3, "fp16": 4}
+LATERAL = {"pad": 0, "stuff": 1}
+EVANESCENT = {"decay": 0, "zero": 1}
+
+
+class PamError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_lib().pam_status_string(status).decode()} ({status})")
+        self.status = status
+
+
+class GeometryC(C.Structure):
+    _fields_ = [("n_elements", C.c_int32), ("pitch_m", C.c_double), ("fs_hz", C.c_double),
+                ("c_mps", C.c_double), ("n_samples", C.c_int32), ("n_bands", C.c_int32),
+                ("band_lo_hz", C.POINTER(C.c_double)), ("band_hi_hz", C.POINTER(C.c_double)),
+                ("n_depths", C.c_int32), ("depths_m", C.POINTER(C.c_double)), ("n_x", C.c_int32),
+                ("lateral", C.c_int), ("n_sub", C.c_int32), ("apod", C.POINTER(C.c_uint8)),
+                ("pattern_m", C.c_int32), ("eps", C.c_double), ("precision", C.c_int),
+                ("evanescent", C.c_int)]
+
+
+class PlanInfoC(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("n_z", C.c_int32), ("n_x", C.c_int32), ("n_sub", C.c_int32),
+                ("n_elements", C.c_int32), ("n_samples", C.c_int32), ("n_pairs", C.c_int32),
+                ("device", C.c_int32)]
+
+
+class LayoutC(C.Structure):
+    _fields_ = [("spectra", C.c_size_t), ("coeffs", C.c_size_t), ("scales", C.c_size_t),
+                ("accum", C.c_size_t), ("energy", C.c_size_t), ("weight", C.c_size_t),
+                ("blockmax", C.c_size_t), ("total", C.c_size_t), ("n_sel", C.c_int32),
+                ("n_split", C.c_int32), ("n_acc", C.c_int32)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run paper_2412_02413_amd/build.py or __graft_entry__.build())")
+        lib = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        lib.pam_plan.argtypes = [C.POINTER(GeometryC), C.c_int, C.POINTER(vp)]
+        lib.pam_plan.restype = C.c_int
+        lib.pam_plan_get_info.argtypes = [vp, C.POINTER(PlanInfoC)]
+        lib.pam_plan_get_info.restype = C.c_int
+        lib.pam_plan_get_bins.argtypes = [vp, C.POINTER(i32), i32]
+        lib.pam_plan_get_bins.restype = C.c_int
+        lib.pam_workspace_size.argtypes = [vp, i64, i32, C.POINTER(sz)]
+        lib.pam_workspace_size.restype = C.c_int
+        lib.pam_workspace_layout.argtypes = [vp, i64, i32, C.POINTER(LayoutC)]
+        lib.pam_workspace_layout.restype = C.c_int
+        lib.pam_as_tax.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]
+        lib.pam_as_tax.restype = C.c_int
+        lib.pam_destroy.argtypes = [vp]
+        lib.pam_destroy.restype = None
+        lib.pam_status_string.argtypes = [C.c_int]
+        lib.pam_status_string.restype = C.c_char_p
+        _LIB = lib
+    return _LIB
+
+
+def _check(status: int, what: str):
+    if status != PAM_OK:
+        raise PamError(status, what)
+
+
+def geometry_struct(geom, precision: Optional[str] = None):
+    """Marshal a Geometry (synth.Geometry or anything with the same fields) into pam_geometry_t.
+
+    Returns the struct and the numpy arrays it points into (keep them alive)."""
+    lo = np.ascontiguousarray([b[0] for b in geom.bands_hz], dtype=np.float64)
+    hi = np.ascontiguousarray([b[1] for b in geom.bands_hz], dtype=np.float64)
+    z = np.ascontiguousarray(geom.depths_m, dtype=np.float64)
+    keep = [lo, hi, z]
+    g = GeometryC()
+    g.n_elements = geom.n_elements
+    g.pitch_m = geom.pitch_m
+    g.fs_hz = geom.fs_hz
+    g.c_mps = geom.c_mps
+    g.n_samples = geom.n_samples
+    g.n_bands = len(lo)
+    g.band_lo_hz = lo.ctypes.data_as(C.POINTER(C.c_double))
+    g.band_hi_hz = hi.ctypes.data_as(C.POINTER(C.c_double))
+    g.n_depths = len(z)
+    g.depths_m = z.ctypes.data_as(C.POINTER(C.c_double))
+    g.n_x = geom.n_x
+    g.lateral = LATERAL[geom.lateral]
+    g.n_sub = geom.n_sub
+    if getattr(geom, "apod", None) is not None:
+        ap = np.ascontiguousarray(geom.apod, dtype=np.uint8)
+        keep.append(ap)
+        g.apod = ap.ctypes.data_as(C.POINTER(C.c_uint8))
+    else:
+        g.apod = None
+    g.pattern_m = getattr(geom, "pattern_m", 16)
+    g.eps = geom.eps
+    g.precision = PRECISIONS[precision or getattr(geom, "precision", "fp32")]
+    g.evanescent = EVANESCENT[geom.evanescent]
+    return g, keep
+
+
+@dataclass
+class Plan:
+    handle: int
+    geom: object
+    precision: str
+    info: PlanInfoC
+
+    @property
+    def n_z(self):
+        return self.info.n_z
+
+    @property
+    def n_x(self):
+        return self.info.n_x
+
+    @property
+    def n_pairs(self):
+        return self.info.n_pairs
+
+
+def pam_plan(geom, device: int = 0, precision: str = "fp32") -> Plan:
+    g, keep = geometry_struct(geom, precision)
+    h = C.c_void_p()
+    _check(_lib().pam_plan(C.byref(g), device, C.byref(h)), "pam_plan")
+    info = PlanInfoC()
+    _check(_lib().pam_plan_get_info(h, C.byref(info)), "pam_plan_get_info")
+    del keep
+    return Plan(h.value, geom, precision, info)
+
+
+def pam_destroy(plan: Plan) -> None:
+    if plan is not None and plan.handle:
+        _lib().pam_destroy(C.c_void_p(plan.handle))
+        plan.handle = 0
+
+
+def pam_plan_get_bins(plan: Plan) -> np.ndarray:
+    out = np.zeros(plan.info.n_bins, dtype=np.int32)
+    _check(_lib().pam_plan_get_bins(C.c_void_p(plan.handle), out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    len(out)), "pam_plan_get_bins")
+    return out
+
+
+def pam_workspace_size(plan: Plan, n_frames: int, n_t: Optional[int] = None) -> int:
+    n = C.c_size_t()
+    n_t = plan.info.n_samples if n_t is None else n_t
+    _check(_lib().pam_workspace_size(C.c_void_p(plan.handle), n_frames, n_t, C.byref(n)), "pam_workspace_size")
+    return n.value
+
+
+def pam_workspace_layout(plan: Plan, n_frames: int, n_t: Optional[int] = None) -> LayoutC:
+    lay = LayoutC()
+    n_t = plan.info.n_samples if n_t is None else n_t
+    _check(_lib().pam_workspace_layout(C.c_void_p(plan.handle), n_frames, n_t, C.byref(lay)),
+           "pam_workspace_layout")
+    return lay
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def pam_as_tax(plan: Plan, rf, image, nncc=None, rho_pairs=None, workspace=None, stream=None,
+               n_t: Optional[int] = None) -> None:
+    """Enqueue one reconstruction of rf [F][L][n_t] (device float32) on `stream`."""
+    import torch
+    F = int(rf.shape[0])
+    n_t = int(rf.shape[-1]) if n_t is None else n_t
+    if stream is None:
+        stream = torch.cuda.current_stream(rf.device)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    st = _lib().pam_as_tax(C.c_void_p(plan.handle), _ptr(rf), F, n_t, _ptr(image), _ptr(nncc),
+                           _ptr(rho_pairs), _ptr(workspace), ws_bytes, C.c_void_p(stream.cuda_stream))
+    _check(st, "pam_as_tax")
+
+
+def alloc_workspace(plan: Plan, n_frames: int, n_t: Optional[int] = None, device="cuda"):
+    import torch
+    n = pam_workspace_size(plan, n_frames, n_t)
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def reconstruct(plan: Plan, rf, want_nncc=True, want_pairs=False, workspace=None, stream=None):
+    """Allocate outputs (and a workspace if none is given), run pam_as_tax, return a dict."""
+    import torch
+    F, n_t = int(rf.shape[0]), int(rf.shape[-1])
+    dev = rf.device
+    out = {"image": torch.empty((F, plan.n_z, plan.n_x), dtype=torch.float32, device=dev)}
+    out["nncc"] = torch.empty_like(out["image"]) if want_nncc else None
+    out["rho_pairs"] = (torch.empty((F, plan.n_pairs, plan.n_z, plan.n_x), dtype=torch.float32, device=dev)
+                        if want_pairs and plan.n_pairs else None)
+    ws = alloc_workspace(plan, F, n_t, dev) if workspace is None else workspace
+    pam_as_tax(plan, rf, out["image"], out["nncc"], out["rho_pairs"], ws, stream, n_t)
+    out["workspace"] = ws
+    return out
