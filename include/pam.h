@@ -97,7 +97,7 @@ typedef struct {
   const double* band_hi_hz;  /* [n_bands], lo <= hi                                       */
   int32_t n_depths;          /* n_z >= 1                                                  */
   const double* depths_m;    /* [n_z], finite, >= 0, measured from the array plane        */
-  int32_t n_x;               /* N_x lateral columns: multiple of 32, >= L, <= 1024        */
+  int32_t n_x;               /* N_x lateral columns: multiple of 32, >= L, <= 512         */
   pam_lateral_t lateral;
   int32_t n_sub;             /* 1 (AS), 2 (AS-DAX) or 3 (AS-TAX)                          */
   const uint8_t* apod;       /* [n_sub][L] masks in {0,1}, or NULL for Pattern-m          */
@@ -158,6 +158,20 @@ pam_status_t pam_workspace_layout(pam_plan_t p, int64_t n_frames, int32_t n_t,
 pam_status_t pam_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t,
                         float* image, float* nncc, float* rho_pairs,
                         void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Number of HIP events pam_as_tax_events records: before K1 (time FFT), after K1,
+ * after K2 (lateral transform), after K3 (fields and cross-spectra), after K4
+ * (weight, NNCC and image). */
+#define PAM_N_STAGE_EVENTS 5
+
+/* pam_as_tax that also records the caller's HIP events (hipEvent_t handles created
+ * by the caller with timing enabled, array of PAM_N_STAGE_EVENTS) on hip_stream at
+ * the stage boundaries, so a caller can time each kernel on the stream it runs on.
+ * Same arguments, validation and results as pam_as_tax; events may not be NULL. */
+pam_status_t pam_as_tax_events(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t,
+                               float* image, float* nncc, float* rho_pairs,
+                               void* workspace, size_t ws_bytes, void* hip_stream,
+                               void* const* events);
 
 /* Release the plan's device tables.  NULL-safe; no work may be in flight. */
 void pam_destroy(pam_plan_t p);

@@ -123,33 +123,50 @@ struct K2Args {
   float* inv_scale;       // [F][n_sel]
   const float2* twx;      // e^{-2 pi i m / N}, m < N
   const float* masks;     // [n_sub][L]
-  const int32_t* cols;    // [L] grid column of each element
   int32_t L, N, n_sub, n_sel;
+  int32_t col0, col_step; // grid column of element l is col0 + col_step * l
 };
 
+template <int NSUB>
 __global__ __launch_bounds__(256) void k2_lateral(K2Args a) {
   extern __shared__ float2 sm2[];
   const int N = a.N;
-  float2* u = sm2;                    // [L]
-  float2* P = sm2 + a.L;              // [n_sub][N] lateral spectra
+  float2* tw = sm2;                   // [N]
+  float2* u = tw + N;                 // [n_sub][L] apodized element spectra
+  float2* P = u + 3 * a.L;            // [n_sub][N] lateral spectra
   float2* Gf = P + a.n_sub * N;       // [n_sub][N] folded coefficients
   __shared__ float red[256];
   const int b = blockIdx.x, f = blockIdx.y;
   const size_t fb = (size_t)f * a.n_sel + b;
-  for (int l = threadIdx.x; l < a.L; l += blockDim.x) u[l] = a.spectra[fb * a.L + l];
+  for (int m = threadIdx.x; m < N; m += blockDim.x) tw[m] = a.twx[m];
+  for (int l = threadIdx.x; l < a.L; l += blockDim.x) {
+    const float2 v = a.spectra[fb * a.L + l];
+    for (int i = 0; i < a.n_sub; ++i) {
+      const float mk = a.masks[i * a.L + l];
+      u[i * a.L + l] = make_float2(mk * v.x, mk * v.y);
+    }
+  }
   __syncthreads();
   for (int q = threadIdx.x; q < N; q += blockDim.x) {
-    float2 acc[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    float2 acc[NSUB];
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) acc[i] = make_float2(0.f, 0.f);
+    // twiddle index (q * column) mod N, advanced by (q * col_step) mod N per element
+    int m = (int)(((unsigned)q * (unsigned)a.col0) % (unsigned)N);
+    const int dm = (int)(((unsigned)q * (unsigned)a.col_step) % (unsigned)N);
     for (int l = 0; l < a.L; ++l) {
-      const int m = (int)(((long long)q * a.cols[l]) % N);
-      const float2 t = cmul(u[l], a.twx[m]);
-      for (int i = 0; i < a.n_sub; ++i) {
-        const float mk = a.masks[i * a.L + l];
-        acc[i].x = fmaf(mk, t.x, acc[i].x);
-        acc[i].y = fmaf(mk, t.y, acc[i].y);
+      const float2 w = tw[m];
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) {
+        const float2 v = u[i * a.L + l];
+        acc[i].x = fmaf(v.x, w.x, fmaf(-v.y, w.y, acc[i].x));
+        acc[i].y = fmaf(v.x, w.y, fmaf(v.y, w.x, acc[i].y));
       }
+      m += dm;
+      if (m >= N) m -= N;
     }
-    for (int i = 0; i < a.n_sub; ++i) P[i * N + q] = acc[i];
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) P[i * N + q] = acc[i];
   }
   __syncthreads();
   // fold into slot order and find the largest magnitude component
@@ -211,7 +228,9 @@ struct K3Args {
   const double* kz;        // [n_bins_plan][N/2 + 1] signed kz
   const double* z;         // [n_z]
   const int32_t* sel;      // [n_sel] plan bin index of each selected bin
-  const float* basis;      // [N][N] slot-major fixed real basis
+  const float* basis;      // [N][N] slot-major fixed real basis (FP32 kernel)
+  const void* basis_hi;    // [N x][N slots] transposed basis, 16-bit hi part (split kernels)
+  const void* basis_lo;    // [N x][N slots] transposed basis, 16-bit lo part
   float* accum;            // [n_split][F][n_acc][n_z][N]
   int32_t N, n_z, n_sel, F, n_dt, n_xg, n_split, bins_per_split, zero_evanescent;
 };
@@ -325,6 +344,172 @@ __global__ __launch_bounds__(NW * 64, 1) void k3_fields_fp32(K3Args a) {
   }
   // 32x32 accumulator layout: lane holds column (lane & 31) and rows
   // 8*(v/4) + 4*(lane/32) + v%4 for v = 0..15.
+  constexpr int NA = AccCount<NSUB>::total;
+  const size_t plane = (size_t)a.n_z * N;
+  float* dst = a.accum + ((size_t)sp * a.F + f) * NA * plane;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int row = d0 + 8 * (v >> 2) + 4 * half + (v & 3);
+    if (row < a.n_z) {
+      const size_t o = (size_t)row * N + x0 + col;
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) dst[i * plane + o] = accS[i][v];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) dst[(NSUB + p) * plane + o] = accC[p][v];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// K3, split precision: the same fused kernel with 16-bit matrix-core operands.
+// Each operand x is split x = hi + lo with hi = round16(x), lo = round16(x - hi)
+// (BF16 or FP16).  PASSES = 3 accumulates hi*hi + hi*lo + lo*hi in FP32 (the
+// lo*lo term is below the FP32 rounding of the sum); PASSES = 1 keeps hi*hi.
+// The phase, its reduction and the sine/cosine are as in the FP32 kernel; the
+// split happens once, when A is written to LDS.  FP16 relies on the power-of-two
+// pre-scaling of the coefficients (largest in [2^11, 2^12)), which keeps the
+// products in range and the lo parts of the significant terms normal.
+// A in LDS: [tile][hi/lo][row][KC + 8] (row padding against bank conflicts);
+// B from the transposed hi/lo basis [x][slot] in L2, 16 bytes per lane per step.
+// --------------------------------------------------------------------------
+template <typename T>
+struct Mma;
+template <>
+struct Mma<__bf16> {
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ v16f run(v8 a, v8 b, v16f c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mma<_Float16> {
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ v16f run(v8 a, v8 b, v16f c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T>
+struct Pair16 {
+  T x, y;
+};
+
+template <typename T, int PASSES, int NSUB, int NW, int KC>
+__global__ __launch_bounds__(NW * 64, 1) void k3_fields_split(K3Args a) {
+  typedef typename Mma<T>::v8 v8;
+  constexpr int NT = 2 * NSUB;
+  constexpr int NP = AccCount<NSUB>::pairs;
+  constexpr int RS = KC + 8;  // row stride (elements) of an A tile in LDS
+  extern __shared__ float smem[];
+  T* As = reinterpret_cast<T*>(smem);                                    // [NT][2][32][RS]
+  float2* Gs = reinterpret_cast<float2*>(smem + (NT * 2 * 32 * RS) / 2);  // [NSUB][N]
+
+  const int N = a.N;
+  const int HQ = N / 2 + 1;
+  int bid = blockIdx.x;
+  const int sp = bid % a.n_split; bid /= a.n_split;
+  const int xg = bid % a.n_xg;    bid /= a.n_xg;
+  const int dt = bid % a.n_dt;    bid /= a.n_dt;
+  const int f = bid;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int x0 = (xg * NW + w) * 32;
+  const int d0 = dt * 32;
+  const int b_begin = sp * a.bins_per_split;
+  const int b_end = min(a.n_sel, b_begin + a.bins_per_split);
+  const int half = lane >> 5, col = lane & 31;
+  const T* bhi = reinterpret_cast<const T*>(a.basis_hi) + (size_t)(x0 + col) * N + 8 * half;
+  const T* blo = reinterpret_cast<const T*>(a.basis_lo) + (size_t)(x0 + col) * N + 8 * half;
+
+  float accS[NSUB][16];
+  float accC[NP > 0 ? NP : 1][16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) accS[i][v] = 0.f;
+#pragma unroll
+    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
+  }
+
+  for (int b = b_begin; b < b_end; ++b) {
+    const size_t fb = (size_t)f * a.n_sel + b;
+    const float2* gsrc = a.coeffs + fb * NSUB * N;
+    for (int e = tid; e < NSUB * N; e += NW * 64) Gs[e] = gsrc[e];
+    const float inv = a.inv_scale[fb];
+    const double* kzb = a.kz + (size_t)a.sel[b] * HQ;
+    __syncthreads();
+
+    v16f C[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) C[t][v] = 0.f;
+
+    for (int c0 = 0; c0 < N; c0 += KC) {
+      for (int e = tid; e < 32 * (KC / 2); e += NW * 64) {
+        const int r = e & 31, ql = e >> 5;
+        const int q = (c0 >> 1) + ql;
+        const int d = d0 + r;
+        float2 h0 = make_float2(0.f, 0.f), h1 = h0;
+        if (d < a.n_z) {
+          const double zd = a.z[d];
+          h0 = propagator(zd, kzb[q], a.zero_evanescent);
+          h1 = (q == 0) ? propagator(zd, kzb[N / 2], a.zero_evanescent) : h0;
+        }
+#pragma unroll
+        for (int i = 0; i < NSUB; ++i) {
+          const float2 a0 = cmul(h0, Gs[i * N + 2 * q]);
+          const float2 a1 = cmul(h1, Gs[i * N + 2 * q + 1]);
+          const float vals[2][2] = {{a0.x, a1.x}, {a0.y, a1.y}};  // [re/im][slot 2ql, 2ql+1]
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) {
+            Pair16<T> hi, lo;
+            hi.x = (T)vals[ri][0];
+            hi.y = (T)vals[ri][1];
+            lo.x = (T)(vals[ri][0] - (float)hi.x);
+            lo.y = (T)(vals[ri][1] - (float)hi.y);
+            const int t = 2 * i + ri;
+            *reinterpret_cast<Pair16<T>*>(As + ((t * 2 + 0) * 32 + r) * RS + 2 * ql) = hi;
+            if (PASSES == 3) *reinterpret_cast<Pair16<T>*>(As + ((t * 2 + 1) * 32 + r) * RS + 2 * ql) = lo;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < KC / 16; ++ks) {
+        const v8 bh = *reinterpret_cast<const v8*>(bhi + c0 + ks * 16);
+        v8 bl;
+        if (PASSES == 3) bl = *reinterpret_cast<const v8*>(blo + c0 + ks * 16);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const v8 ah = *reinterpret_cast<const v8*>(As + ((t * 2 + 0) * 32 + col) * RS + ks * 16 + 8 * half);
+          C[t] = Mma<T>::run(ah, bh, C[t]);
+          if (PASSES == 3) {
+            const v8 al = *reinterpret_cast<const v8*>(As + ((t * 2 + 1) * 32 + col) * RS + ks * 16 + 8 * half);
+            C[t] = Mma<T>::run(ah, bl, C[t]);
+            C[t] = Mma<T>::run(al, bh, C[t]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float pr[NSUB], pim[NSUB];
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) {
+        pr[i] = C[2 * i][v] * inv;
+        pim[i] = C[2 * i + 1][v] * inv;
+        accS[i][v] = fmaf(pr[i], pr[i], fmaf(pim[i], pim[i], accS[i][v]));
+      }
+      if constexpr (NSUB == 3) {
+        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
+        accC[1][v] = fmaf(pr[1], pr[2], fmaf(pim[1], pim[2], accC[1][v]));
+        accC[2][v] = fmaf(pr[2], pr[0], fmaf(pim[2], pim[0], accC[2][v]));
+      } else if constexpr (NSUB == 2) {
+        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
+      }
+    }
+  }
   constexpr int NA = AccCount<NSUB>::total;
   const size_t plane = (size_t)a.n_z * N;
   float* dst = a.accum + ((size_t)sp * a.F + f) * NA * plane;

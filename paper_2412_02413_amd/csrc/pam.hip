@@ -17,7 +17,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMinSamples = 32;
 constexpr int kMaxSamples = 16384;
-constexpr int kMaxNx = 1024;
+constexpr int kMaxNx = 512;
 
 struct DeviceGuard {
   int prev = -1;
@@ -50,6 +50,34 @@ int ilog2(int v) {
 }
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// round-to-nearest-even FP32 -> BF16 / FP16 bit patterns, and back
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float from_bf16(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+uint16_t to_fp16(float f) {
+  const _Float16 h = (_Float16)f;
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+float from_fp16(uint16_t u) {
+  _Float16 h;
+  std::memcpy(&h, &u, 2);
+  return (float)h;
+}
+bool is_split(int prec) { return prec != PAM_PREC_FP32; }
+bool is_fp16(int prec) { return prec == PAM_PREC_SPLIT_FP16 || prec == PAM_PREC_FP16; }
+int passes(int prec) { return (prec == PAM_PREC_SPLIT_BF16 || prec == PAM_PREC_SPLIT_FP16) ? 3 : 1; }
+
 }  // namespace
 
 struct pam_plan_s {
@@ -65,8 +93,10 @@ struct pam_plan_s {
   float2* d_tw = nullptr;      // [n_t/2] time-FFT twiddles
   float2* d_twx = nullptr;     // [N] lateral DFT twiddles
   float* d_masks = nullptr;    // [n_sub][L]
-  int32_t* d_cols = nullptr;   // [L]
-  float* d_basis = nullptr;    // [N][N] slot-major cos/sin basis
+  int32_t col0 = 0, col_step = 1;  // grid column of element l: col0 + col_step * l
+  float* d_basis = nullptr;    // [N][N] slot-major cos/sin basis (FP32 kernel)
+  uint16_t* d_bhi = nullptr;   // [N][N] transposed basis, 16-bit hi (split kernels)
+  uint16_t* d_blo = nullptr;   // [N][N] transposed basis, 16-bit lo
   std::vector<void*> allocs;
 };
 
@@ -117,7 +147,6 @@ pam_status_t validate(const pam_geometry_t* g) {
   }
   if (!(g->eps >= 0.0 && g->eps < 1.0)) return PAM_ERR_INVALID_ARG;
   if (g->precision < PAM_PREC_FP32 || g->precision > PAM_PREC_FP16) return PAM_ERR_INVALID_ARG;
-  if (g->precision != PAM_PREC_FP32) return PAM_ERR_UNSUPPORTED;
   if (g->evanescent != PAM_EVAN_DECAY && g->evanescent != PAM_EVAN_ZERO) return PAM_ERR_INVALID_ARG;
   return PAM_OK;
 }
@@ -153,7 +182,8 @@ LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
   s.n_dt = (p->n_z + 31) / 32;
   s.nw = waves_for(p->N);
   s.n_xg = p->N / (32 * s.nw);
-  s.kc = (p->N > 512) ? 32 : 64;
+  // FP32: 64-slot chunks; 16-bit split: 64-slot chunks up to N = 256, 32 beyond (64 KiB LDS)
+  s.kc = (is_split(p->precision) && p->N > 256) ? 32 : 64;
   const int64_t base = F * s.n_dt * s.n_xg;
   int split = 1;
   if (base > 0 && base < 512) {
@@ -220,10 +250,52 @@ hipError_t launch_k3_nw(int nw, const pam::K3Args& a, int blocks, hipStream_t st
 
 template <int NSUB>
 hipError_t launch_k3_kc(int kc, int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
-  return kc == 32 ? launch_k3_nw<NSUB, 32>(nw, a, blocks, st) : launch_k3_nw<NSUB, 64>(nw, a, blocks, st);
+  (void)kc;  // one chunk size: 64 slots (LDS: 48 KiB of A + n_sub N complex coefficients)
+  return launch_k3_nw<NSUB, 64>(nw, a, blocks, st);
 }
 
-hipError_t launch_k3(int n_sub, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
+// split-precision kernels: LDS = A tiles [2 n_sub][hi, lo][32][KC + 8] 16-bit + coefficients
+template <typename T, int P, int NSUB, int NW, int KC>
+hipError_t launch_split_t(const pam::K3Args& a, int blocks, hipStream_t st) {
+  const size_t lds = (size_t)(2 * NSUB) * 2 * 32 * (KC + 8) * 2 + (size_t)NSUB * a.N * sizeof(float2);
+  hipLaunchKernelGGL((pam::k3_fields_split<T, P, NSUB, NW, KC>), dim3(blocks), dim3(NW * 64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int P, int NSUB, int KC>
+hipError_t launch_split_nw(int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
+  switch (nw) {
+    case 8: return launch_split_t<T, P, NSUB, 8, KC>(a, blocks, st);
+    case 4: return launch_split_t<T, P, NSUB, 4, KC>(a, blocks, st);
+    case 2: return launch_split_t<T, P, NSUB, 2, KC>(a, blocks, st);
+    default: return launch_split_t<T, P, NSUB, 1, KC>(a, blocks, st);
+  }
+}
+
+template <typename T, int P, int NSUB>
+hipError_t launch_split_kc(int kc, int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
+  return kc == 32 ? launch_split_nw<T, P, NSUB, 32>(nw, a, blocks, st)
+                  : launch_split_nw<T, P, NSUB, 64>(nw, a, blocks, st);
+}
+
+template <typename T, int P>
+hipError_t launch_split(int n_sub, int kc, int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
+  switch (n_sub) {
+    case 3: return launch_split_kc<T, P, 3>(kc, nw, a, blocks, st);
+    case 2: return launch_split_kc<T, P, 2>(kc, nw, a, blocks, st);
+    default: return launch_split_kc<T, P, 1>(kc, nw, a, blocks, st);
+  }
+}
+
+hipError_t launch_k3(int precision, int n_sub, const LaunchShape& s, const pam::K3Args& a, int blocks,
+                     hipStream_t st) {
+  switch (precision) {
+    case PAM_PREC_SPLIT_BF16: return launch_split<__bf16, 3>(n_sub, s.kc, s.nw, a, blocks, st);
+    case PAM_PREC_SPLIT_FP16: return launch_split<_Float16, 3>(n_sub, s.kc, s.nw, a, blocks, st);
+    case PAM_PREC_BF16: return launch_split<__bf16, 1>(n_sub, s.kc, s.nw, a, blocks, st);
+    case PAM_PREC_FP16: return launch_split<_Float16, 1>(n_sub, s.kc, s.nw, a, blocks, st);
+    default: break;
+  }
   switch (n_sub) {
     case 3: return launch_k3_kc<3>(s.kc, s.nw, a, blocks, st);
     case 2: return launch_k3_kc<2>(s.kc, s.nw, a, blocks, st);
@@ -275,16 +347,15 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
   const int L = p->L, N = p->N, HQ = N / 2 + 1;
 
   // lateral placement: grid column of each element and grid spacing
-  std::vector<int32_t> cols(L);
   double dx;
   if (g->lateral == PAM_LATERAL_PAD) {
-    const int o = (N - L) / 2;
-    for (int l = 0; l < L; ++l) cols[l] = o + l;
+    p->col0 = (N - L) / 2;
+    p->col_step = 1;
     dx = g->pitch_m;
   } else {
-    const int s = N / L;
-    for (int l = 0; l < L; ++l) cols[l] = s * l;
-    dx = g->pitch_m / s;
+    p->col0 = 0;
+    p->col_step = N / L;
+    dx = g->pitch_m / p->col_step;
   }
   // apodization masks: explicit or Pattern-m (a_i[l] = 1 iff floor(l/m) mod n == i)
   std::vector<float> masks((size_t)p->n_sub * L, 0.f);
@@ -330,13 +401,31 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     }
   }
 
+  std::vector<uint16_t> bhi, blo;
+  if (is_split(p->precision)) {
+    bhi.resize((size_t)N * N);
+    blo.resize((size_t)N * N);
+    const bool h16 = is_fp16(p->precision);
+    for (int s = 0; s < N; ++s)
+      for (int x = 0; x < N; ++x) {
+        const float v = basis[(size_t)s * N + x];
+        const uint16_t hi = h16 ? to_fp16(v) : to_bf16(v);
+        const float r = v - (h16 ? from_fp16(hi) : from_bf16(hi));
+        bhi[(size_t)x * N + s] = hi;
+        blo[(size_t)x * N + s] = h16 ? to_fp16(r) : to_bf16(r);
+      }
+  }
+
   do {
     if ((st = upload(p, &p->d_kz, kz.data(), kz.size())) != PAM_OK) break;
+    if (is_split(p->precision)) {
+      if ((st = upload(p, &p->d_bhi, bhi.data(), bhi.size())) != PAM_OK) break;
+      if ((st = upload(p, &p->d_blo, blo.data(), blo.size())) != PAM_OK) break;
+    }
     if ((st = upload(p, &p->d_z, z.data(), z.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_tw, tw.data(), tw.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_twx, twx.data(), twx.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_masks, masks.data(), masks.size())) != PAM_OK) break;
-    if ((st = upload(p, &p->d_cols, cols.data(), cols.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_basis, basis.data(), basis.size())) != PAM_OK) break;
     // bin subsets for records of n_t / 2^j samples
     for (int stride = 1; p->n_t / stride >= kMinSamples; stride <<= 1) {
@@ -395,10 +484,15 @@ pam_status_t pam_workspace_size(pam_plan_t p, int64_t n_frames, int32_t n_t, siz
   return st;
 }
 
-pam_status_t pam_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
-                        float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
+                        float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream,
+                        void* const* events) {
   if (!p || n_frames < 0) return PAM_ERR_INVALID_ARG;
-  if (n_frames > (int64_t)1 << 20) return PAM_ERR_UNSUPPORTED;
+  if (n_frames > 65535) return PAM_ERR_UNSUPPORTED;
   pam_workspace_layout_t W;
   pam_status_t st = layout(p, n_frames, n_t, &W);
   if (st != PAM_OK) return st;
@@ -419,28 +513,39 @@ pam_status_t pam_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   float* weight = reinterpret_cast<float*>(ws + W.weight);
   float* blockmax = reinterpret_cast<float*>(ws + W.blockmax);
   const int F = (int)n_frames;
+  auto mark = [&](int i) -> bool {
+    return !events || hipEventRecord(static_cast<hipEvent_t>(events[i]), stream) == hipSuccess;
+  };
+  if (!mark(0)) return PAM_ERR_DEVICE;
 
   // K1: time FFT, one workgroup per (channel, frame)
   {
     pam::K1Args a{rf, spectra, p->d_tw, lv->d_ksel, p->L, n_t, ilog2(n_t / 2), lv->stride, lv->n_sel};
     hipLaunchKernelGGL(pam::k1_time_fft, dim3(p->L, F), dim3(256), (size_t)(n_t / 2) * sizeof(float2), stream, a);
-    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
+    if (hipGetLastError() != hipSuccess || !mark(1)) return PAM_ERR_DEVICE;
   }
   // K2: lateral DFT + fold, one workgroup per (bin, frame)
   {
-    pam::K2Args a{spectra, coeffs, scales, p->d_twx, p->d_masks, p->d_cols, p->L, p->N, p->n_sub, lv->n_sel};
-    const size_t lds = (size_t)(p->L + 2 * p->n_sub * p->N) * sizeof(float2);
-    hipLaunchKernelGGL(pam::k2_lateral, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
-    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
+    pam::K2Args a{spectra, coeffs, scales, p->d_twx, p->d_masks, p->L, p->N, p->n_sub, lv->n_sel,
+                  p->col0, p->col_step};
+    const size_t lds = (size_t)(p->N + 3 * p->L + 2 * p->n_sub * p->N) * sizeof(float2);
+    if (p->n_sub == 3)
+      hipLaunchKernelGGL(pam::k2_lateral<3>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+    else if (p->n_sub == 2)
+      hipLaunchKernelGGL(pam::k2_lateral<2>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+    else
+      hipLaunchKernelGGL(pam::k2_lateral<1>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+    if (hipGetLastError() != hipSuccess || !mark(2)) return PAM_ERR_DEVICE;
   }
   // K3: fused propagate / inverse lateral transform / cross-spectra
   {
     const LaunchShape s = k3_shape(p, F, lv->n_sel);
-    pam::K3Args a{coeffs, scales, p->d_kz, p->d_z, lv->d_sel, p->d_basis, accum,
+    pam::K3Args a{coeffs, scales, p->d_kz, p->d_z, lv->d_sel, p->d_basis, p->d_bhi, p->d_blo, accum,
                   p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
     if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
-    if (launch_k3(p->n_sub, s, a, (int)blocks, stream) != hipSuccess) return PAM_ERR_DEVICE;
+    if (launch_k3(p->precision, p->n_sub, s, a, (int)blocks, stream) != hipSuccess || !mark(3))
+      return PAM_ERR_DEVICE;
   }
   // K4: NCC / weight / energy, then NNCC and image
   {
@@ -450,9 +555,27 @@ pam_status_t pam_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
     hipLaunchKernelGGL(pam::k4_weight, dim3(n_blk, F), dim3(256), 0, stream, a);
     if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
     hipLaunchKernelGGL(pam::k4_image, dim3(n_blk, F), dim3(256), 0, stream, a);
-    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
+    if (hipGetLastError() != hipSuccess || !mark(4)) return PAM_ERR_DEVICE;
   }
   return PAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pam_status_t pam_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
+                        float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream) {
+  return run_as_tax(p, rf, n_frames, n_t, image, nncc, rho_pairs, workspace, ws_bytes, hip_stream, nullptr);
+}
+
+pam_status_t pam_as_tax_events(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
+                               float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes,
+                               void* hip_stream, void* const* events) {
+  if (!events) return PAM_ERR_INVALID_ARG;
+  for (int i = 0; i < PAM_N_STAGE_EVENTS; ++i)
+    if (!events[i]) return PAM_ERR_INVALID_ARG;
+  return run_as_tax(p, rf, n_frames, n_t, image, nncc, rho_pairs, workspace, ws_bytes, hip_stream, events);
 }
 
 void pam_destroy(pam_plan_t p) { free_plan(p); }

@@ -57,6 +57,9 @@ _LIB = None
 def _lib():
     global _LIB
     if _LIB is None:
+        # torch first: its HIP runtime (same soname) is then the one libpam binds to,
+        # so torch streams and device pointers are valid in the library.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                                "(run paper_2412_02413_amd/build.py or __graft_entry__.build())")
@@ -74,6 +77,8 @@ def _lib():
         lib.pam_workspace_layout.restype = C.c_int
         lib.pam_as_tax.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]
         lib.pam_as_tax.restype = C.c_int
+        lib.pam_as_tax_events.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp, C.POINTER(vp)]
+        lib.pam_as_tax_events.restype = C.c_int
         lib.pam_destroy.argtypes = [vp]
         lib.pam_destroy.restype = None
         lib.pam_status_string.argtypes = [C.c_int]
@@ -196,6 +201,60 @@ def pam_as_tax(plan: Plan, rf, image, nncc=None, rho_pairs=None, workspace=None,
     st = _lib().pam_as_tax(C.c_void_p(plan.handle), _ptr(rf), F, n_t, _ptr(image), _ptr(nncc),
                            _ptr(rho_pairs), _ptr(workspace), ws_bytes, C.c_void_p(stream.cuda_stream))
     _check(st, "pam_as_tax")
+
+
+N_STAGE_EVENTS = 5
+STAGES = ("time_fft", "lateral", "fields", "finalize")
+
+
+def pam_as_tax_events(plan: Plan, rf, image, events, nncc=None, rho_pairs=None, workspace=None,
+                      stream=None, n_t: Optional[int] = None) -> None:
+    """pam_as_tax recording N_STAGE_EVENTS raw hipEvent_t handles at the stage boundaries."""
+    import torch
+    F = int(rf.shape[0])
+    n_t = int(rf.shape[-1]) if n_t is None else n_t
+    if stream is None:
+        stream = torch.cuda.current_stream(rf.device)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    arr = (C.c_void_p * N_STAGE_EVENTS)(*events)
+    st = _lib().pam_as_tax_events(C.c_void_p(plan.handle), _ptr(rf), F, n_t, _ptr(image), _ptr(nncc),
+                                  _ptr(rho_pairs), _ptr(workspace), ws_bytes,
+                                  C.c_void_p(stream.cuda_stream), arr)
+    _check(st, "pam_as_tax_events")
+
+
+class HipEvents:
+    """Raw HIP timing events from the process's HIP runtime (plumbing for timing only)."""
+
+    def __init__(self):
+        _lib()
+        self.rt = C.CDLL("libamdhip64.so.7")
+        self.rt.hipEventCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
+        self.rt.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [C.c_void_p]
+        self.rt.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.live = []
+
+    def create(self, n: int):
+        out = []
+        for _ in range(n):
+            e = C.c_void_p()
+            if self.rt.hipEventCreateWithFlags(C.byref(e), 0) != 0:
+                raise RuntimeError("hipEventCreateWithFlags failed")
+            out.append(e.value)
+        self.live += out
+        return out
+
+    def elapsed_ms(self, a, b) -> float:
+        ms = C.c_float()
+        if self.rt.hipEventElapsedTime(C.byref(ms), C.c_void_p(a), C.c_void_p(b)) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def close(self):
+        for e in self.live:
+            self.rt.hipEventDestroy(C.c_void_p(e))
+        self.live = []
 
 
 def alloc_workspace(plan: Plan, n_frames: int, n_t: Optional[int] = None, device="cuda"):

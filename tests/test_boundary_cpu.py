@@ -45,6 +45,7 @@ def plan_status(geom, precision="fp32"):
     (dict(n_x=48), P.PAM_ERR_INVALID_ARG),                # N_x < L
     (dict(n_x=144), P.PAM_ERR_UNSUPPORTED),               # not a multiple of 32
     (dict(n_samples=1000), P.PAM_ERR_UNSUPPORTED),        # not a power of two
+    (dict(n_x=1024), P.PAM_ERR_UNSUPPORTED),              # wider than the kernels' LDS tiles
     (dict(n_samples=32768), P.PAM_ERR_UNSUPPORTED),       # beyond the LDS FFT
     (dict(bands_hz=[(6e6, 5e6)]), P.PAM_ERR_INVALID_ARG), # lo > hi
     (dict(bands_hz=[(9.99e6, 9.999e6)]), P.PAM_ERR_INVALID_ARG),  # no bin in band

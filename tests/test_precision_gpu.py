@@ -1,0 +1,98 @@
+"""Split-precision forms of the inverse lateral transform against the FP64 oracle.
+
+Tolerances: split BF16 / split FP16 (three 16-bit products, FP32 accumulation):
+relative L2 error of the image <= 1e-3 and absolute NNCC error <= 1e-3.  The
+single-product BF16 / FP16 forms are reported; they are held to a looser
+bound (1e-2 on the image, 5e-2 on the NNCC) that only guards against gross
+failure: a single 16-bit product does not reach 1e-3 on the NNCC.
+"""
+import numpy as np
+import pytest
+
+from oracle import as_tax as O
+from paper_2412_02413_amd import synth
+
+pytestmark = pytest.mark.gpu
+MM = 1e-3
+BOUND = {"split_bf16": (1e-3, 1e-3), "split_fp16": (1e-3, 1e-3), "bf16": (1e-2, 5e-2), "fp16": (1e-2, 5e-2)}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2412_02413_amd import pam
+    assert torch.cuda.is_available()
+    pam._lib()
+    return torch, pam
+
+
+def gpu_run(env, geom, rf, precision):
+    torch, pam = env
+    plan = pam.pam_plan(geom, 0, precision)
+    try:
+        x = torch.from_numpy(np.ascontiguousarray(rf, np.float32)).cuda()
+        out = pam.reconstruct(plan, x, want_nncc=True)
+        torch.cuda.synchronize()
+        return out["image"].cpu().numpy(), out["nncc"].cpu().numpy()
+    finally:
+        pam.pam_destroy(plan)
+
+
+def errors(img, rho, ref):
+    e_i = float(np.linalg.norm(img - ref["I"]) / np.linalg.norm(ref["I"]))
+    e_r = float(np.abs(rho - ref["rho_n"]).max())
+    return e_i, e_r
+
+
+@pytest.fixture(scope="module")
+def cfg1_refs():
+    g = synth.cfg1_geometry()
+    rf = synth.batch(synth.cfg1_frame, [40, 41])
+    return g, rf, [O.as_tax(rf[f], g) for f in range(2)]
+
+
+@pytest.mark.parametrize("precision", ["split_bf16", "split_fp16", "bf16", "fp16"])
+def test_precision_cfg1(env, cfg1_refs, precision):
+    g, rf, refs = cfg1_refs
+    img, rho = gpu_run(env, g, rf, precision)
+    tol_i, tol_r = BOUND[precision]
+    for f in range(2):
+        e_i, e_r = errors(img[f], rho[f], refs[f])
+        print(f"{precision}: frame {f} relL2(I)={e_i:.3e} max|d rho_n|={e_r:.3e}", flush=True)
+        assert e_i <= tol_i and e_r <= tol_r
+
+
+@pytest.mark.parametrize("precision", ["split_bf16", "split_fp16"])
+def test_precision_cfg2_reduced(env, precision):
+    g = synth.cfg2_geometry()
+    g = g.replace(depths_m=g.depths_m[np.linspace(0, 511, 40).astype(int)])
+    rf, _ = synth.cfg2_frame(6)
+    img, rho = gpu_run(env, g, rf[None], precision)
+    e_i, e_r = errors(img[0], rho[0], O.as_tax(rf, g))
+    print(f"{precision} cfg2: relL2(I)={e_i:.3e} max|d rho_n|={e_r:.3e}", flush=True)
+    assert e_i <= 1e-3 and e_r <= 1e-3
+
+
+def test_mixed_record_lengths_on_one_plan(env):
+    """64 frames of the cfg1 array with record lengths drawn from {2048, 4096, 8192} on one
+    8192-sample plan, one launch per record length.  Split results are checked against the
+    FP32 path on every frame and against the oracle on one frame of each length."""
+    torch, pam = env
+    g = synth.cfg3_geometry()
+    frames = [synth.cfg3_frame(s) for s in range(64)]
+    lengths = sorted({fr.shape[-1] for fr in frames})
+    assert len(lengths) >= 2
+    for n_t in lengths:
+        idx = [i for i, fr in enumerate(frames) if fr.shape[-1] == n_t]
+        rf = np.stack([frames[i] for i in idx])
+        img32, rho32 = gpu_run(env, g, rf, "fp32")
+        for prec in ("split_bf16", "split_fp16"):
+            img, rho = gpu_run(env, g, rf, prec)
+            for k in range(len(idx)):
+                e = float(np.linalg.norm(img[k] - img32[k]) / np.linalg.norm(img32[k]))
+                assert e <= 1e-3 and float(np.abs(rho[k] - rho32[k]).max()) <= 1e-3
+        ref = O.as_tax(rf[0], g.replace(n_samples=n_t))
+        e_i, e_r = errors(img32[0], rho32[0], ref)
+        print(f"n_t={n_t} ({len(idx)} frames): fp32 vs oracle relL2(I)={e_i:.3e} max|d rho_n|={e_r:.3e}",
+              flush=True)
+        assert e_i <= 1e-5 and e_r <= 1e-4
