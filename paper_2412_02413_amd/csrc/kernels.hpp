@@ -32,8 +32,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr double kTwoPiHi = 6.283185307179586232;      // 2 pi rounded to FP64
-constexpr double kTwoPiLo = 2.4492935982947064e-16;    // 2 pi - kTwoPiHi
-constexpr double kInvTwoPi = 0.15915494309189533577;
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -41,22 +39,20 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// exp(i z kz) for one (depth, lateral wavenumber).  kzs >= 0 is a propagating
-// kz; kzs < 0 encodes an evanescent component decaying at rate -kzs.  The phase
-// z*kz is formed and reduced modulo 2 pi in FP64 (|z kz| reaches thousands of
-// radians), then the sine and cosine of the reduced angle are taken in FP32.
-__device__ __forceinline__ float2 propagator(double z, double kzs, int zero_evanescent) {
-  if (kzs >= 0.0) {
-    const double ph = z * kzs;
-    const double n = rint(ph * kInvTwoPi);
-    double r = fma(-n, kTwoPiHi, ph);
-    r = fma(-n, kTwoPiLo, r);
-    float s, c;
-    sincosf((float)r, &s, &c);
-    return make_float2(c, s);
+// exp(i z kz) for one (depth, lateral wavenumber).  The table holds kz / (2 pi)
+// in cycles per metre: kzc >= 0 is a propagating component, kzc < 0 encodes an
+// evanescent one decaying as exp(2 pi z kzc).  The phase z*kz/(2 pi) (thousands
+// of cycles at depth) is formed and reduced to [-1/2, 1/2] cycle in FP64; the
+// sine and cosine of the reduced phase come from the hardware transcendental
+// unit, whose argument is in cycles (max abs error ~1.2e-7 on [-1/2, 1/2]).
+__device__ __forceinline__ float2 propagator(double z, double kzc, int zero_evanescent) {
+  if (kzc >= 0.0) {
+    const double ph = z * kzc;
+    const float r = (float)(ph - rint(ph));
+    return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
   }
   if (zero_evanescent) return make_float2(0.f, 0.f);
-  return make_float2(expf((float)(z * kzs)), 0.f);
+  return make_float2(expf((float)(kTwoPiHi * z * kzc)), 0.f);
 }
 
 // --------------------------------------------------------------------------
@@ -208,24 +204,12 @@ __global__ __launch_bounds__(256) void k2_lateral(K2Args a) {
 }
 
 // --------------------------------------------------------------------------
-// K3: fused propagate + inverse lateral transform + cross-spectra over bins.
-//
-// GEMM view for one (frame, bin): rows = depths, K = N slots, columns = x.
-//   A_t[d, s] = Re or Im of H(d, q(s)) * coeff_i[s]   (t = 2 i + {0: re, 1: im})
-//   B[s, x]   = basis (cos / sin), fixed
-//   p_i(d, x) = (A_{2i} B)(d, x) + i (A_{2i+1} B)(d, x)
-// A workgroup owns a 32-depth tile and NW 32-column x tiles (one per wave) of one
-// frame, and a contiguous range of bins.  Per bin it stages the frame's
-// coefficients in LDS, generates A chunk by chunk in LDS (each (d, q) phase once,
-// shared by all sub-apertures, both slots and all waves), and each wave runs
-// 2*NSUB 32x32 FP32 matrix-core tiles over K with B read from the L2-resident
-// basis.  The finished fields of the bin are folded into six per-pixel register
-// accumulators and discarded.
+// K3 arguments (kernels in k3_fields.hpp).
 // --------------------------------------------------------------------------
 struct K3Args {
   const float2* coeffs;    // [F][n_sel][n_sub][N] slot order
   const float* inv_scale;  // [F][n_sel]
-  const double* kz;        // [n_bins_plan][N/2 + 1] signed kz
+  const double* kz;        // [n_bins_plan][N/2 + 1] signed kz / (2 pi), cycles per metre
   const double* z;         // [n_z]
   const int32_t* sel;      // [n_sel] plan bin index of each selected bin
   const float* basis;      // [N][N] slot-major fixed real basis (FP32 kernel)
@@ -241,137 +225,7 @@ struct AccCount {
   static constexpr int total = NSUB + pairs;
 };
 
-template <int NSUB, int NW, int KC>
-__global__ __launch_bounds__(NW * 64, 1) void k3_fields_fp32(K3Args a) {
-  constexpr int NT = 2 * NSUB;
-  constexpr int NP = AccCount<NSUB>::pairs;
-  // KC: slots per LDS chunk
-  extern __shared__ float smem[];
-  float* As = smem;                                         // [NT][KC][32]
-  float2* Gs = reinterpret_cast<float2*>(smem + NT * KC * 32);  // [NSUB][N]
-
-  const int N = a.N;
-  const int HQ = N / 2 + 1;
-  int bid = blockIdx.x;
-  const int sp = bid % a.n_split; bid /= a.n_split;
-  const int xg = bid % a.n_xg;    bid /= a.n_xg;
-  const int dt = bid % a.n_dt;    bid /= a.n_dt;
-  const int f = bid;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int x0 = (xg * NW + w) * 32;
-  const int d0 = dt * 32;
-  const int b_begin = sp * a.bins_per_split;
-  const int b_end = min(a.n_sel, b_begin + a.bins_per_split);
-  const int half = lane >> 5, col = lane & 31;
-
-  float accS[NSUB][16];
-  float accC[NP > 0 ? NP : 1][16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i) accS[i][v] = 0.f;
-#pragma unroll
-    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
-  }
-
-  for (int b = b_begin; b < b_end; ++b) {
-    const size_t fb = (size_t)f * a.n_sel + b;
-    const float2* gsrc = a.coeffs + fb * NSUB * N;
-    for (int e = tid; e < NSUB * N; e += NW * 64) Gs[e] = gsrc[e];
-    const float inv = a.inv_scale[fb];
-    const double* kzb = a.kz + (size_t)a.sel[b] * HQ;
-    __syncthreads();
-
-    v16f C[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) C[t][v] = 0.f;
-
-    for (int c0 = 0; c0 < N; c0 += KC) {
-      // A chunk: slots c0 .. c0+KC-1  <->  q = c0/2 .. c0/2 + KC/2 - 1
-      for (int e = tid; e < 32 * (KC / 2); e += NW * 64) {
-        const int r = e & 31, ql = e >> 5;
-        const int q = (c0 >> 1) + ql;
-        const int d = d0 + r;
-        float2 h0 = make_float2(0.f, 0.f), h1 = h0;
-        if (d < a.n_z) {
-          const double zd = a.z[d];
-          h0 = propagator(zd, kzb[q], a.zero_evanescent);
-          h1 = (q == 0) ? propagator(zd, kzb[N / 2], a.zero_evanescent) : h0;
-        }
-#pragma unroll
-        for (int i = 0; i < NSUB; ++i) {
-          const float2 a0 = cmul(h0, Gs[i * N + 2 * q]);
-          const float2 a1 = cmul(h1, Gs[i * N + 2 * q + 1]);
-          As[((2 * i + 0) * KC + 2 * ql + 0) * 32 + r] = a0.x;
-          As[((2 * i + 1) * KC + 2 * ql + 0) * 32 + r] = a0.y;
-          As[((2 * i + 0) * KC + 2 * ql + 1) * 32 + r] = a1.x;
-          As[((2 * i + 1) * KC + 2 * ql + 1) * 32 + r] = a1.y;
-        }
-      }
-      __syncthreads();
-      const float* bp = a.basis + (size_t)(c0 + half) * N + x0 + col;
-#pragma unroll 4
-      for (int j = 0; j < KC / 2; ++j) {
-        const float bv = bp[(size_t)(2 * j) * N];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const float av = As[(t * KC + 2 * j + half) * 32 + col];
-          C[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, C[t], 0, 0, 0);
-        }
-      }
-      __syncthreads();
-    }
-    // fold this bin's fields into the per-pixel sums
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      float pr[NSUB], pim[NSUB];
-#pragma unroll
-      for (int i = 0; i < NSUB; ++i) {
-        pr[i] = C[2 * i][v] * inv;
-        pim[i] = C[2 * i + 1][v] * inv;
-        accS[i][v] = fmaf(pr[i], pr[i], fmaf(pim[i], pim[i], accS[i][v]));
-      }
-      if constexpr (NSUB == 3) {
-        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
-        accC[1][v] = fmaf(pr[1], pr[2], fmaf(pim[1], pim[2], accC[1][v]));
-        accC[2][v] = fmaf(pr[2], pr[0], fmaf(pim[2], pim[0], accC[2][v]));
-      } else if constexpr (NSUB == 2) {
-        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
-      }
-    }
-  }
-  // 32x32 accumulator layout: lane holds column (lane & 31) and rows
-  // 8*(v/4) + 4*(lane/32) + v%4 for v = 0..15.
-  constexpr int NA = AccCount<NSUB>::total;
-  const size_t plane = (size_t)a.n_z * N;
-  float* dst = a.accum + ((size_t)sp * a.F + f) * NA * plane;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int row = d0 + 8 * (v >> 2) + 4 * half + (v & 3);
-    if (row < a.n_z) {
-      const size_t o = (size_t)row * N + x0 + col;
-#pragma unroll
-      for (int i = 0; i < NSUB; ++i) dst[i * plane + o] = accS[i][v];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) dst[(NSUB + p) * plane + o] = accC[p][v];
-    }
-  }
-}
-
-// --------------------------------------------------------------------------
-// K3, split precision: the same fused kernel with 16-bit matrix-core operands.
-// Each operand x is split x = hi + lo with hi = round16(x), lo = round16(x - hi)
-// (BF16 or FP16).  PASSES = 3 accumulates hi*hi + hi*lo + lo*hi in FP32 (the
-// lo*lo term is below the FP32 rounding of the sum); PASSES = 1 keeps hi*hi.
-// The phase, its reduction and the sine/cosine are as in the FP32 kernel; the
-// split happens once, when A is written to LDS.  FP16 relies on the power-of-two
-// pre-scaling of the coefficients (largest in [2^11, 2^12)), which keeps the
-// products in range and the lo parts of the significant terms normal.
-// A in LDS: [tile][hi/lo][row][KC + 8] (row padding against bank conflicts);
-// B from the transposed hi/lo basis [x][slot] in L2, 16 bytes per lane per step.
-// --------------------------------------------------------------------------
+// 16-bit matrix-core products used by the split-precision K3 kernels.
 template <typename T>
 struct Mma;
 template <>
@@ -393,138 +247,6 @@ template <typename T>
 struct Pair16 {
   T x, y;
 };
-
-template <typename T, int PASSES, int NSUB, int NW, int KC>
-__global__ __launch_bounds__(NW * 64, 1) void k3_fields_split(K3Args a) {
-  typedef typename Mma<T>::v8 v8;
-  constexpr int NT = 2 * NSUB;
-  constexpr int NP = AccCount<NSUB>::pairs;
-  constexpr int RS = KC + 8;  // row stride (elements) of an A tile in LDS
-  extern __shared__ float smem[];
-  T* As = reinterpret_cast<T*>(smem);                                    // [NT][2][32][RS]
-  float2* Gs = reinterpret_cast<float2*>(smem + (NT * 2 * 32 * RS) / 2);  // [NSUB][N]
-
-  const int N = a.N;
-  const int HQ = N / 2 + 1;
-  int bid = blockIdx.x;
-  const int sp = bid % a.n_split; bid /= a.n_split;
-  const int xg = bid % a.n_xg;    bid /= a.n_xg;
-  const int dt = bid % a.n_dt;    bid /= a.n_dt;
-  const int f = bid;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int x0 = (xg * NW + w) * 32;
-  const int d0 = dt * 32;
-  const int b_begin = sp * a.bins_per_split;
-  const int b_end = min(a.n_sel, b_begin + a.bins_per_split);
-  const int half = lane >> 5, col = lane & 31;
-  const T* bhi = reinterpret_cast<const T*>(a.basis_hi) + (size_t)(x0 + col) * N + 8 * half;
-  const T* blo = reinterpret_cast<const T*>(a.basis_lo) + (size_t)(x0 + col) * N + 8 * half;
-
-  float accS[NSUB][16];
-  float accC[NP > 0 ? NP : 1][16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i) accS[i][v] = 0.f;
-#pragma unroll
-    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
-  }
-
-  for (int b = b_begin; b < b_end; ++b) {
-    const size_t fb = (size_t)f * a.n_sel + b;
-    const float2* gsrc = a.coeffs + fb * NSUB * N;
-    for (int e = tid; e < NSUB * N; e += NW * 64) Gs[e] = gsrc[e];
-    const float inv = a.inv_scale[fb];
-    const double* kzb = a.kz + (size_t)a.sel[b] * HQ;
-    __syncthreads();
-
-    v16f C[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) C[t][v] = 0.f;
-
-    for (int c0 = 0; c0 < N; c0 += KC) {
-      for (int e = tid; e < 32 * (KC / 2); e += NW * 64) {
-        const int r = e & 31, ql = e >> 5;
-        const int q = (c0 >> 1) + ql;
-        const int d = d0 + r;
-        float2 h0 = make_float2(0.f, 0.f), h1 = h0;
-        if (d < a.n_z) {
-          const double zd = a.z[d];
-          h0 = propagator(zd, kzb[q], a.zero_evanescent);
-          h1 = (q == 0) ? propagator(zd, kzb[N / 2], a.zero_evanescent) : h0;
-        }
-#pragma unroll
-        for (int i = 0; i < NSUB; ++i) {
-          const float2 a0 = cmul(h0, Gs[i * N + 2 * q]);
-          const float2 a1 = cmul(h1, Gs[i * N + 2 * q + 1]);
-          const float vals[2][2] = {{a0.x, a1.x}, {a0.y, a1.y}};  // [re/im][slot 2ql, 2ql+1]
-#pragma unroll
-          for (int ri = 0; ri < 2; ++ri) {
-            Pair16<T> hi, lo;
-            hi.x = (T)vals[ri][0];
-            hi.y = (T)vals[ri][1];
-            lo.x = (T)(vals[ri][0] - (float)hi.x);
-            lo.y = (T)(vals[ri][1] - (float)hi.y);
-            const int t = 2 * i + ri;
-            *reinterpret_cast<Pair16<T>*>(As + ((t * 2 + 0) * 32 + r) * RS + 2 * ql) = hi;
-            if (PASSES == 3) *reinterpret_cast<Pair16<T>*>(As + ((t * 2 + 1) * 32 + r) * RS + 2 * ql) = lo;
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int ks = 0; ks < KC / 16; ++ks) {
-        const v8 bh = *reinterpret_cast<const v8*>(bhi + c0 + ks * 16);
-        v8 bl;
-        if (PASSES == 3) bl = *reinterpret_cast<const v8*>(blo + c0 + ks * 16);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const v8 ah = *reinterpret_cast<const v8*>(As + ((t * 2 + 0) * 32 + col) * RS + ks * 16 + 8 * half);
-          C[t] = Mma<T>::run(ah, bh, C[t]);
-          if (PASSES == 3) {
-            const v8 al = *reinterpret_cast<const v8*>(As + ((t * 2 + 1) * 32 + col) * RS + ks * 16 + 8 * half);
-            C[t] = Mma<T>::run(ah, bl, C[t]);
-            C[t] = Mma<T>::run(al, bh, C[t]);
-          }
-        }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      float pr[NSUB], pim[NSUB];
-#pragma unroll
-      for (int i = 0; i < NSUB; ++i) {
-        pr[i] = C[2 * i][v] * inv;
-        pim[i] = C[2 * i + 1][v] * inv;
-        accS[i][v] = fmaf(pr[i], pr[i], fmaf(pim[i], pim[i], accS[i][v]));
-      }
-      if constexpr (NSUB == 3) {
-        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
-        accC[1][v] = fmaf(pr[1], pr[2], fmaf(pim[1], pim[2], accC[1][v]));
-        accC[2][v] = fmaf(pr[2], pr[0], fmaf(pim[2], pim[0], accC[2][v]));
-      } else if constexpr (NSUB == 2) {
-        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
-      }
-    }
-  }
-  constexpr int NA = AccCount<NSUB>::total;
-  const size_t plane = (size_t)a.n_z * N;
-  float* dst = a.accum + ((size_t)sp * a.F + f) * NA * plane;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int row = d0 + 8 * (v >> 2) + 4 * half + (v & 3);
-    if (row < a.n_z) {
-      const size_t o = (size_t)row * N + x0 + col;
-#pragma unroll
-      for (int i = 0; i < NSUB; ++i) dst[i * plane + o] = accS[i][v];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) dst[(NSUB + p) * plane + o] = accC[p][v];
-    }
-  }
-}
 
 // --------------------------------------------------------------------------
 // K4: NCC, weight, energy, NNCC and image.

@@ -11,6 +11,7 @@
 
 #include "../../include/pam.h"
 #include "kernels.hpp"
+#include "k3_fields.hpp"
 
 namespace {
 
@@ -88,7 +89,7 @@ struct pam_plan_s {
   std::vector<int32_t> bins;  // k on the plan grid
   std::vector<Level> levels;
   // device tables
-  double* d_kz = nullptr;      // [n_bins][N/2+1] signed kz
+  double* d_kz = nullptr;      // [n_bins][N/2+1] signed kz / (2 pi)
   double* d_z = nullptr;       // [n_z]
   float2* d_tw = nullptr;      // [n_t/2] time-FFT twiddles
   float2* d_twx = nullptr;     // [N] lateral DFT twiddles
@@ -166,24 +167,18 @@ std::vector<int32_t> select_bins(const pam_geometry_t* g) {
   return ks;
 }
 
-int waves_for(int N) {
-  const int tiles = N / 32;
-  for (int nw : {8, 4, 2, 1})
-    if (tiles % nw == 0) return nw;
-  return 1;
-}
-
 struct LaunchShape {
-  int n_dt, nw, n_xg, n_split, bins_per_split, kc;
+  int n_dt, nw, xt, n_xg, n_split, bins_per_split;
 };
 
 LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
   LaunchShape s;
   s.n_dt = (p->n_z + 31) / 32;
-  s.nw = waves_for(p->N);
-  s.n_xg = p->N / (32 * s.nw);
-  // FP32: 64-slot chunks; 16-bit split: 64-slot chunks up to N = 256, 32 beyond (64 KiB LDS)
-  s.kc = (is_split(p->precision) && p->N > 256) ? 32 : 64;
+  const int tiles = p->N / 32;
+  s.nw = (tiles % 4 == 0) ? 4 : (tiles % 2 == 0 ? 2 : 1);
+  // nw consumer waves (one 32-column tile each) and as many producer waves
+  s.xt = 1;
+  s.n_xg = p->N / (32 * s.nw * s.xt);
   const int64_t base = F * s.n_dt * s.n_xg;
   int split = 1;
   if (base > 0 && base < 512) {
@@ -231,75 +226,46 @@ pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layou
   return PAM_OK;
 }
 
-template <int NSUB, int NW, int KC>
-hipError_t launch_k3_t(const pam::K3Args& a, int blocks, hipStream_t st) {
-  const size_t lds = (size_t)(2 * NSUB) * KC * 32 * sizeof(float) + (size_t)NSUB * a.N * sizeof(float2);
-  hipLaunchKernelGGL((pam::k3_fields_fp32<NSUB, NW, KC>), dim3(blocks), dim3(NW * 64), lds, st, a);
+// K3 kernels: NC consumer + NC producer waves, NC*32 columns per workgroup.
+// LDS above 64 KiB needs the per-kernel attribute.
+template <typename K>
+hipError_t launch_with_lds(K kernel, int nc, size_t lds, const pam::K3Args& a, int blocks, hipStream_t st) {
+  static const hipError_t attr =
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(nc * 128), lds, st, a);
   return hipGetLastError();
 }
 
-template <int NSUB, int KC>
-hipError_t launch_k3_nw(int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
-  switch (nw) {
-    case 8: return launch_k3_t<NSUB, 8, KC>(a, blocks, st);
-    case 4: return launch_k3_t<NSUB, 4, KC>(a, blocks, st);
-    case 2: return launch_k3_t<NSUB, 2, KC>(a, blocks, st);
-    default: return launch_k3_t<NSUB, 1, KC>(a, blocks, st);
+template <int NSUB, int NC>
+hipError_t launch_prec(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+  switch (precision) {
+    case PAM_PREC_SPLIT_BF16:
+      return launch_with_lds(pam::k3_fields_split<__bf16, 3, NSUB, NC>, NC, pam::k3_split_lds<3, NSUB, NC>(), a, blocks, st);
+    case PAM_PREC_SPLIT_FP16:
+      return launch_with_lds(pam::k3_fields_split<_Float16, 3, NSUB, NC>, NC, pam::k3_split_lds<3, NSUB, NC>(), a, blocks, st);
+    case PAM_PREC_BF16:
+      return launch_with_lds(pam::k3_fields_split<__bf16, 1, NSUB, NC>, NC, pam::k3_split_lds<1, NSUB, NC>(), a, blocks, st);
+    case PAM_PREC_FP16:
+      return launch_with_lds(pam::k3_fields_split<_Float16, 1, NSUB, NC>, NC, pam::k3_split_lds<1, NSUB, NC>(), a, blocks, st);
+    default:
+      return launch_with_lds(pam::k3_fields_fp32<NSUB, NC>, NC, pam::k3_fp32_lds<NSUB, NC>(), a, blocks, st);
   }
 }
 
 template <int NSUB>
-hipError_t launch_k3_kc(int kc, int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
-  (void)kc;  // one chunk size: 64 slots (LDS: 48 KiB of A + n_sub N complex coefficients)
-  return launch_k3_nw<NSUB, 64>(nw, a, blocks, st);
-}
-
-// split-precision kernels: LDS = A tiles [2 n_sub][hi, lo][32][KC + 8] 16-bit + coefficients
-template <typename T, int P, int NSUB, int NW, int KC>
-hipError_t launch_split_t(const pam::K3Args& a, int blocks, hipStream_t st) {
-  const size_t lds = (size_t)(2 * NSUB) * 2 * 32 * (KC + 8) * 2 + (size_t)NSUB * a.N * sizeof(float2);
-  hipLaunchKernelGGL((pam::k3_fields_split<T, P, NSUB, NW, KC>), dim3(blocks), dim3(NW * 64), lds, st, a);
-  return hipGetLastError();
-}
-
-template <typename T, int P, int NSUB, int KC>
-hipError_t launch_split_nw(int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
-  switch (nw) {
-    case 8: return launch_split_t<T, P, NSUB, 8, KC>(a, blocks, st);
-    case 4: return launch_split_t<T, P, NSUB, 4, KC>(a, blocks, st);
-    case 2: return launch_split_t<T, P, NSUB, 2, KC>(a, blocks, st);
-    default: return launch_split_t<T, P, NSUB, 1, KC>(a, blocks, st);
-  }
-}
-
-template <typename T, int P, int NSUB>
-hipError_t launch_split_kc(int kc, int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
-  return kc == 32 ? launch_split_nw<T, P, NSUB, 32>(nw, a, blocks, st)
-                  : launch_split_nw<T, P, NSUB, 64>(nw, a, blocks, st);
-}
-
-template <typename T, int P>
-hipError_t launch_split(int n_sub, int kc, int nw, const pam::K3Args& a, int blocks, hipStream_t st) {
-  switch (n_sub) {
-    case 3: return launch_split_kc<T, P, 3>(kc, nw, a, blocks, st);
-    case 2: return launch_split_kc<T, P, 2>(kc, nw, a, blocks, st);
-    default: return launch_split_kc<T, P, 1>(kc, nw, a, blocks, st);
-  }
+hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
+  if (s.nw == 4) return launch_prec<NSUB, 4>(precision, a, blocks, st);
+  if (s.nw == 2) return launch_prec<NSUB, 2>(precision, a, blocks, st);
+  return launch_prec<NSUB, 1>(precision, a, blocks, st);
 }
 
 hipError_t launch_k3(int precision, int n_sub, const LaunchShape& s, const pam::K3Args& a, int blocks,
                      hipStream_t st) {
-  switch (precision) {
-    case PAM_PREC_SPLIT_BF16: return launch_split<__bf16, 3>(n_sub, s.kc, s.nw, a, blocks, st);
-    case PAM_PREC_SPLIT_FP16: return launch_split<_Float16, 3>(n_sub, s.kc, s.nw, a, blocks, st);
-    case PAM_PREC_BF16: return launch_split<__bf16, 1>(n_sub, s.kc, s.nw, a, blocks, st);
-    case PAM_PREC_FP16: return launch_split<_Float16, 1>(n_sub, s.kc, s.nw, a, blocks, st);
-    default: break;
-  }
   switch (n_sub) {
-    case 3: return launch_k3_kc<3>(s.kc, s.nw, a, blocks, st);
-    case 2: return launch_k3_kc<2>(s.kc, s.nw, a, blocks, st);
-    default: return launch_k3_kc<1>(s.kc, s.nw, a, blocks, st);
+    case 3: return launch_shape<3>(precision, s, a, blocks, st);
+    case 2: return launch_shape<2>(precision, s, a, blocks, st);
+    default: return launch_shape<1>(precision, s, a, blocks, st);
   }
 }
 
@@ -363,14 +329,16 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
   for (int i = 0; i < p->n_sub; ++i)
     for (int l = 0; l < L; ++l)
       masks[(size_t)i * L + l] = g->apod ? (float)g->apod[(size_t)i * L + l] : (((l / m) % p->n_sub) == i ? 1.f : 0.f);
-  // signed kz for the folded half grid q = 0..N/2: kx_q = 2 pi q / (N dx)
+  // kz / (2 pi) in cycles per metre for the folded half grid q = 0..N/2:
+  // k / (2 pi) = f / c and kx_q / (2 pi) = q / (N dx); negative values mark
+  // evanescent components (decay rate / (2 pi)).
   std::vector<double> kz((size_t)p->n_bins * HQ);
   for (int b = 0; b < p->n_bins; ++b) {
     const double f = ((double)ks[b] * g->fs_hz) / (double)g->n_samples;
-    const double k = 2.0 * kPi * f / g->c_mps;
+    const double kc = f / g->c_mps;
     for (int q = 0; q < HQ; ++q) {
-      const double kx = 2.0 * kPi * (double)q / ((double)N * dx);
-      const double d = k * k - kx * kx;
+      const double kxc = (double)q / ((double)N * dx);
+      const double d = kc * kc - kxc * kxc;
       kz[(size_t)b * HQ + q] = d >= 0.0 ? std::sqrt(d) : -std::sqrt(-d);
     }
   }
