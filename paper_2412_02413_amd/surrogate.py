@@ -1,0 +1,382 @@
+"""Learned NCC-mask surrogate for AS-TAX.
+
+AS-TAX forms its image as I = rho_n^2 * E (Eq. 11) where E is the energy of the
+summed sub-aperture fields and rho_n the normalised TAX weight (Eq. 10), which
+costs three angular-spectrum propagations.  With complementary masks, E equals
+the plain full-aperture AS image (Eq. 3), which costs one.  The surrogate is a
+U-Net that predicts rho_n from the full-aperture energy alone, plus a per-pixel
+estimate of its own error; a frame whose energy-weighted predicted error is too
+high (confidence below a threshold) falls back to plain AS-TAX.  Plain AS-TAX
+on the GPU generates the training targets and judges the result.
+
+Every numerical step runs in the HIP library: the reconstructions through
+pam_as_tax, the network through the pam_nn_* kernels.  This module owns the
+parameters (FP32 master copies, BF16 packed copies for the matrix cores, Adam
+moments), the activation buffers and the order of the calls.
+"""
+from __future__ import annotations
+
+import math
+import os
+import time
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import nn, pam, synth
+
+C_FEAT = 32   # input channels of the first convolution (2 features, zero padded)
+
+
+@dataclass
+class ConvSpec:
+    name: str
+    c_in: int
+    c_out: int
+
+
+class UNet:
+    """U-Net of `levels` levels with base*2^l channels at level l (see oracle conventions in
+    include/pam_nn.h): two 3x3 convolutions + ReLU per level, 2x2 max pooling, nearest 2x
+    upsampling with skip concatenation [upsampled, skip], a 1x1 head with two outputs."""
+
+    def __init__(self, levels: int = 4, base: int = 32, seed: int = 0, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.levels, self.base = levels, base
+        self.device = torch.device(device)
+        self.ch = [base * 2 ** l for l in range(levels)]
+        self.specs: List[ConvSpec] = []
+        prev = C_FEAT
+        for l in range(levels):
+            self.specs += [ConvSpec(f"enc{l}a", prev, self.ch[l]), ConvSpec(f"enc{l}b", self.ch[l], self.ch[l])]
+            prev = self.ch[l]
+        for l in range(levels - 2, -1, -1):
+            self.specs += [ConvSpec(f"dec{l}a", self.ch[l + 1] + self.ch[l], self.ch[l]),
+                           ConvSpec(f"dec{l}b", self.ch[l], self.ch[l])]
+        self.spec = {s.name: s for s in self.specs}
+        rng = np.random.default_rng(seed)
+        host = {}
+        for s in self.specs:
+            fan_in = 9 * (2 if s.name == "enc0a" else s.c_in)
+            w = np.zeros((9, s.c_in, s.c_out))
+            live = 2 if s.name == "enc0a" else s.c_in
+            w[:, :live, :] = rng.standard_normal((9, live, s.c_out)) * math.sqrt(2.0 / fan_in)
+            host[s.name + ".w"] = w
+            host[s.name + ".b"] = np.zeros(s.c_out)
+        host["head.w"] = rng.standard_normal((self.ch[0], 2)) * math.sqrt(1.0 / self.ch[0])
+        host["head.b"] = np.zeros(2)
+        self.load_host_params(host)
+        self.step_count = 0
+        self.cache = {}
+
+    # -- parameters ----------------------------------------------------------------
+    def load_host_params(self, host: Dict[str, np.ndarray]):
+        torch = self.torch
+        self.params = {k: torch.tensor(v, dtype=torch.float32, device=self.device).contiguous() for k, v in host.items()}
+        self.grads = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.m = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.wt, self.wd = {}, {}
+        for s in self.specs:
+            self.wt[s.name] = torch.empty((s.c_out, 9, s.c_in), dtype=torch.bfloat16, device=self.device)
+            self.wd[s.name] = torch.empty((s.c_in, 9, s.c_out), dtype=torch.bfloat16, device=self.device)
+        self.pack()
+
+    def pack(self):
+        for s in self.specs:
+            nn.pack_weights(self.params[s.name + ".w"], s.c_in, s.c_out, self.wt[s.name], self.wd[s.name])
+
+    def host_params(self) -> Dict[str, np.ndarray]:
+        return {k: v.double().cpu().numpy() for k, v in self.params.items()}
+
+    def state_dict(self):
+        return {"levels": self.levels, "base": self.base, "step": self.step_count,
+                **{f"p.{k}": v for k, v in self.params.items()},
+                **{f"m.{k}": v for k, v in self.m.items()}, **{f"v.{k}": v for k, v in self.v.items()}}
+
+    def load_state_dict(self, sd):
+        for k in self.params:
+            self.params[k].copy_(sd[f"p.{k}"])
+            self.m[k].copy_(sd[f"m.{k}"])
+            self.v[k].copy_(sd[f"v.{k}"])
+        self.step_count = int(sd["step"])
+        self.pack()
+
+    # -- forward ---------------------------------------------------------------------
+    def _buf(self, key, shape, dtype=None):
+        torch = self.torch
+        dtype = dtype or torch.bfloat16
+        t = self.cache.get(key)
+        if t is None or tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+            t = torch.empty(shape, dtype=dtype, device=self.device)
+            self.cache[key] = t
+        return t
+
+    def forward(self, x, B: int, H: int, W: int):
+        """x: BF16 [B][H][W][C_FEAT].  Returns (mask, err) FP32 [B][H][W]; keeps activations."""
+        L, ch = self.levels, self.ch
+        self.shape = (B, H, W)
+        self.x = x
+        h, ld_h = x, C_FEAT
+        for l in range(L):
+            Hl, Wl = H >> l, W >> l
+            if l > 0:
+                Hp, Wp = H >> (l - 1), W >> (l - 1)
+                src, ld_src = self.skip_view(l - 1)
+                pooled = self._buf(f"pool{l}", (B, Hl, Wl, ch[l - 1]))
+                arg = self._buf(f"arg{l}", (B, Hl, Wl, ch[l - 1]), self.torch.uint8)
+                nn.maxpool(src, ld_src, B, Hp, Wp, ch[l - 1], pooled, ch[l - 1], arg)
+                h, ld_h = pooled, ch[l - 1]
+            a_out = self._buf(f"enc{l}a", (B, Hl, Wl, ch[l]))
+            s = self.spec[f"enc{l}a"]
+            nn.conv3x3(h, ld_h, B, Hl, Wl, s.c_in, self.wt[s.name], self.params[s.name + ".b"], a_out, ch[l],
+                       ch[l], relu=True)
+            out, ld_out = self.skip_view(l)
+            nn.conv3x3(a_out, ch[l], B, Hl, Wl, ch[l], self.wt[f"enc{l}b"], self.params[f"enc{l}b.b"], out,
+                       ld_out, ch[l], relu=True)
+            h, ld_h = out, ld_out
+        for l in range(L - 2, -1, -1):
+            Hl, Wl = H >> l, W >> l
+            cat = self._buf(f"cat{l}", (B, Hl, Wl, ch[l + 1] + ch[l]))
+            nn.upsample(h, ld_h, B, Hl // 2, Wl // 2, ch[l + 1], cat, ch[l + 1] + ch[l])
+            da = self._buf(f"dec{l}a", (B, Hl, Wl, ch[l]))
+            nn.conv3x3(cat, ch[l + 1] + ch[l], B, Hl, Wl, ch[l + 1] + ch[l], self.wt[f"dec{l}a"],
+                       self.params[f"dec{l}a.b"], da, ch[l], ch[l], relu=True)
+            db = self._buf(f"dec{l}b", (B, Hl, Wl, ch[l]))
+            nn.conv3x3(da, ch[l], B, Hl, Wl, ch[l], self.wt[f"dec{l}b"], self.params[f"dec{l}b.b"], db, ch[l],
+                       ch[l], relu=True)
+            h, ld_h = db, ch[l]
+        self.feat = h
+        mask = self._buf("mask", (B, H, W), self.torch.float32)
+        err = self._buf("err", (B, H, W), self.torch.float32)
+        nn.head(h, ch[0], B * H * W, self.params["head.w"], self.params["head.b"], None, mask, err, None, None,
+                B * H * W)
+        return mask, err
+
+    def skip_view(self, l):
+        """Output of encoder level l: a channel slice of the decoder's concat buffer
+        (channels [C_{l+1}, C_{l+1} + C_l)) except at the deepest level."""
+        B, H, W = self.shape
+        ch = self.ch
+        if l == self.levels - 1:
+            return self._buf(f"enc{l}b", (B, H >> l, W >> l, ch[l])), ch[l]
+        cat = self._buf(f"cat{l}", (B, H >> l, W >> l, ch[l + 1] + ch[l]))
+        return cat.view(-1)[ch[l + 1]:], ch[l + 1] + ch[l]
+
+    # -- loss and backward -------------------------------------------------------------
+    def loss_backward(self, target):
+        """Head loss against target (FP32 [B][H][W]) and gradients of every parameter."""
+        torch = self.torch
+        B, H, W = self.shape
+        L, ch = self.levels, self.ch
+        P0 = B * H * W
+        mask, err = self.cache["mask"], self.cache["err"]
+        dz = self._buf("dz", (P0, 2), torch.float32)
+        loss = self._buf("loss", (2,), torch.float32)
+        loss.zero_()
+        for g in self.grads.values():
+            g.zero_()
+        nn.head(self.feat, ch[0], P0, self.params["head.w"], self.params["head.b"], target, mask, err, dz, loss, P0)
+        d = self._buf("gdec0b", (B, H, W, ch[0]))
+        nn.head_backward(self.feat, ch[0], P0, self.params["head.w"], dz, d, self.grads["head.w"],
+                         self.grads["head.b"])
+
+        def conv_back(name, x, ldx, y, ldy, dy, lddy, Hl, Wl, want_dx, dx=None, lddx=0):
+            s = self.spec[name]
+            nn.relu_backward(y, ldy, dy, lddy, B * Hl * Wl, s.c_out)
+            nn.conv3x3_wgrad(x, ldx, dy, lddy, B, Hl, Wl, s.c_in, s.c_out, self.grads[name + ".w"],
+                             self.grads[name + ".b"])
+            if want_dx:
+                nn.conv3x3(dy, lddy, B, Hl, Wl, s.c_out, self.wd[name], None, dx, lddx, s.c_in, relu=False,
+                           flip=True)
+
+        for l in range(0, L - 1):
+            Hl, Wl = H >> l, W >> l
+            cw = ch[l + 1] + ch[l]
+            gda = self._buf(f"gdec{l}a", (B, Hl, Wl, ch[l]))
+            conv_back(f"dec{l}b", self.cache[f"dec{l}a"], ch[l], self.cache[f"dec{l}b"], ch[l], d, ch[l], Hl, Wl,
+                      True, gda, ch[l])
+            gcat = self._buf(f"gcat{l}", (B, Hl, Wl, cw))
+            conv_back(f"dec{l}a", self.cache[f"cat{l}"], cw, self.cache[f"dec{l}a"], ch[l], gda, ch[l], Hl, Wl,
+                      True, gcat, cw)
+            nxt = self._buf(f"gdec{l + 1}b" if l + 1 <= L - 2 else f"genc{L - 1}b",
+                            (B, Hl // 2, Wl // 2, ch[l + 1]))
+            nn.upsample_backward(gcat, cw, B, Hl // 2, Wl // 2, ch[l + 1], nxt, ch[l + 1])
+            d = nxt
+        ld_d = ch[L - 1]
+        for l in range(L - 1, -1, -1):
+            Hl, Wl = H >> l, W >> l
+            out, ld_out = self.skip_view(l)
+            gea = self._buf(f"genc{l}a", (B, Hl, Wl, ch[l]))
+            conv_back(f"enc{l}b", self.cache[f"enc{l}a"], ch[l], out, ld_out, d, ld_d, Hl, Wl, True, gea, ch[l])
+            if l == 0:
+                conv_back("enc0a", self.x, C_FEAT, self.cache["enc0a"], ch[0], gea, ch[0], Hl, Wl, False)
+            else:
+                gpool = self._buf(f"gpool{l}", (B, Hl, Wl, ch[l - 1]))
+                conv_back(f"enc{l}a", self.cache[f"pool{l}"], ch[l - 1], self.cache[f"enc{l}a"], ch[l], gea, ch[l],
+                          Hl, Wl, True, gpool, ch[l - 1])
+                # gradient at the skip output of level l-1: the decoder's share (already in
+                # the skip slice of gcat{l-1}) plus the pooling path
+                gcat = self._buf(f"gcat{l - 1}", (B, Hl * 2, Wl * 2, ch[l] + ch[l - 1]))
+                gskip = gcat.view(-1)[ch[l]:]
+                nn.maxpool_backward(gpool, ch[l - 1], self.cache[f"arg{l}"], B, Hl * 2, Wl * 2, ch[l - 1], gskip,
+                                    ch[l] + ch[l - 1], True)
+                d, ld_d = gskip, ch[l] + ch[l - 1]
+        return loss
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        for k in self.params:
+            nn.adam(self.params[k], self.grads[k], self.m[k], self.v[k], lr, beta1, beta2, eps, self.step_count)
+        self.pack()
+
+
+# ----------------------------------------------------------------------------
+# Data: frames from the generator, targets from plain AS-TAX on the GPU
+# ----------------------------------------------------------------------------
+
+def _frame(seed):
+    return synth.cfg4_frame(seed)[0]
+
+
+def generate_rf(seeds: Sequence[int], workers: int = 0) -> np.ndarray:
+    if workers and len(seeds) > 32:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            frames = pool.map(_frame, list(seeds), chunksize=16)
+    else:
+        frames = [_frame(s) for s in seeds]
+    return np.stack(frames)
+
+
+class Teacher:
+    """Plain AS-TAX on the GPU: the full-aperture energy E (equal to the AS image for
+    complementary masks) and the NNCC rho_n of each frame."""
+
+    def __init__(self, geom, precision: str = "fp32", max_frames: int = 64):
+        import torch
+        self.torch = torch
+        self.geom = geom
+        self.plan = pam.pam_plan(geom, 0, precision)
+        self.max_frames = max_frames
+        self.ws = pam.alloc_workspace(self.plan, max_frames, geom.n_samples)
+
+    def __call__(self, rf):
+        torch = self.torch
+        F = rf.shape[0]
+        assert F <= self.max_frames
+        lay = pam.pam_workspace_layout(self.plan, F, self.geom.n_samples)
+        img = torch.empty((F, self.plan.n_z, self.plan.n_x), device=rf.device)
+        nncc = torch.empty_like(img)
+        ws = self.ws[:lay.total]
+        pam.pam_as_tax(self.plan, rf, img, nncc, None, ws)
+        pix = self.plan.n_z * self.plan.n_x
+        energy = ws[lay.energy:lay.energy + F * pix * 4].view(torch.float32).view(F, self.plan.n_z, self.plan.n_x)
+        return energy.clone(), nncc, img
+
+    def close(self):
+        pam.pam_destroy(self.plan)
+
+
+def build_dataset(seeds, geom, chunk: int = 64, workers: int = 16, log=None):
+    """Energies and NNCC targets (FP32 device tensors [n][n_z][n_x]) of the given frames."""
+    import torch
+    t = Teacher(geom, max_frames=chunk)
+    E, R = [], []
+    try:
+        for i in range(0, len(seeds), 512):
+            rf = generate_rf(seeds[i:i + 512], workers)
+            for j in range(0, rf.shape[0], chunk):
+                x = torch.from_numpy(rf[j:j + chunk]).cuda()
+                e, r, _ = t(x)
+                E.append(e)
+                R.append(r)
+            if log:
+                log(f"dataset: {min(i + 512, len(seeds))}/{len(seeds)} frames")
+    finally:
+        torch.cuda.synchronize()
+        t.close()
+    return torch.cat(E), torch.cat(R)
+
+
+# ----------------------------------------------------------------------------
+# Training and inference
+# ----------------------------------------------------------------------------
+
+def train(net: UNet, E, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 0, log=None, log_every=50):
+    torch = net.torch
+    n, H, W = E.shape
+    feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
+    rng = np.random.default_rng(seed)
+    hist = []
+    t0 = time.perf_counter()
+    for it in range(steps):
+        idx = torch.as_tensor(rng.choice(n, size=batch, replace=False), device=net.device)
+        e = E.index_select(0, idx).contiguous()
+        r = R.index_select(0, idx).contiguous()
+        nn.features(e, batch, H * W, feats)
+        net.forward(feats, batch, H, W)
+        loss = net.loss_backward(r)
+        net.adam_step(lr=lr)
+        if it % log_every == 0 or it == steps - 1:
+            l = loss.cpu().numpy()
+            hist.append((it, float(l[0]), float(l[1])))
+            if log:
+                log(f"step {it}: mask L1 {l[0]:.4f} err-head L1 {l[1]:.4f} ({time.perf_counter() - t0:.1f} s)")
+    return hist
+
+
+def predict(net: UNet, E, batch: int = 8):
+    """Mask, predicted error and per-frame confidence for energies E [n][H][W]."""
+    torch = net.torch
+    n, H, W = E.shape
+    feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
+    masks, errs, confs = [], [], []
+    for i in range(0, n, batch):
+        b = min(batch, n - i)
+        e = E[i:i + b].contiguous()
+        nn.features(e, b, H * W, feats)
+        m, er = net.forward(feats[:b], b, H, W)
+        c = torch.empty(b, dtype=torch.float32, device=net.device)
+        nn.confidence(er, e, b, H * W, c)
+        masks.append(m.clone())
+        errs.append(er.clone())
+        confs.append(c)
+    return torch.cat(masks), torch.cat(errs), torch.cat(confs)
+
+
+class SurrogatePipeline:
+    """Surrogate AS-TAX: one full-aperture propagation (n_sub = 1 plan) + network mask;
+    frames whose confidence is below tau are recomputed with plain AS-TAX."""
+
+    def __init__(self, geom, net: UNet, tau: float, precision: str = "fp32", max_frames: int = 64):
+        import torch
+        self.torch = torch
+        self.geom, self.net, self.tau = geom, net, tau
+        g1 = geom.replace(n_sub=1, apod=np.ones((1, geom.n_elements), np.uint8))
+        self.plan1 = pam.pam_plan(g1, 0, precision)
+        self.ws1 = pam.alloc_workspace(self.plan1, max_frames, geom.n_samples)
+        self.teacher = Teacher(geom, precision, max_frames)
+
+    def __call__(self, rf):
+        torch = self.torch
+        F = rf.shape[0]
+        H, W = self.plan1.n_z, self.plan1.n_x
+        E = torch.empty((F, H, W), device=rf.device)
+        pam.pam_as_tax(self.plan1, rf, E, None, None, self.ws1)      # plain AS image = E
+        mask, err, conf = predict(self.net, E, batch=min(8, F))
+        image = torch.empty_like(E)
+        nn.apply_mask(mask, E, image)
+        fallback = (conf < self.tau).cpu().numpy()
+        if fallback.any():
+            idx = np.nonzero(fallback)[0]
+            sel = torch.as_tensor(idx, device=rf.device)
+            _, _, img3 = self.teacher(rf.index_select(0, sel).contiguous())
+            image.index_copy_(0, sel, img3)
+        return image, mask, conf, fallback
+
+    def close(self):
+        pam.pam_destroy(self.plan1)
+        self.teacher.close()

@@ -1,0 +1,89 @@
+"""Surrogate network on the GPU: every kernel of the forward and backward pass against the
+FP64 CPU reference (oracle/unet.py) with the same parameters; BF16 operands with FP32
+accumulation bound the agreement (tolerances below)."""
+import numpy as np
+import pytest
+
+from oracle import unet as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2412_02413_amd import nn, pam, surrogate
+    assert torch.cuda.is_available()
+    pam._lib()
+    return torch, nn, surrogate
+
+
+def bf16_round(a):
+    import torch
+    return torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-30))
+
+
+@pytest.mark.parametrize("levels,H,W", [(2, 32, 64), (3, 32, 128)])
+def test_unet_forward_and_gradients_match_reference(env, levels, H, W):
+    torch, nn, S = env
+    B = 2
+    net = S.UNet(levels=levels, base=32, seed=7)
+    rng = np.random.default_rng(11)
+    # random biases so every ReLU path is exercised
+    host = net.host_params()
+    for k in host:
+        if k.endswith(".b"):
+            host[k] = rng.standard_normal(host[k].shape) * 0.05
+    net.load_host_params(host)
+    feats = np.zeros((B, H, W, S.C_FEAT))
+    feats[..., :2] = rng.uniform(0, 1, (B, H, W, 2))
+    target = rng.uniform(0, 1, (B, H, W))
+    x = torch.tensor(feats, dtype=torch.float32).to(torch.bfloat16).cuda()
+    t = torch.tensor(target, dtype=torch.float32).cuda()
+    mask, err = net.forward(x, B, H, W)
+    loss = net.loss_backward(t)
+    torch.cuda.synchronize()
+    gm, ge = mask.cpu().numpy(), err.cpu().numpy()
+    # reference with the BF16-rounded parameters the kernels use
+    ref_p = {k: (bf16_round(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in host.items()}
+    ref_p = {k.replace(".w", ".w"): v for k, v in ref_p.items()}
+    g_ref = {k: np.zeros_like(v) for k, v in host.items()}
+    l_ref = 0.0
+    for b in range(B):
+        m, e, _ = U.forward(ref_p, bf16_round(feats[b]), levels)
+        assert rel(gm[b], m) < 2e-2 and rel(ge[b], e) < 2e-2
+        lb, gb, _ = U.loss_and_grads(ref_p, bf16_round(feats[b]), target[b], levels)
+        l_ref += lb / B
+        for k in gb:
+            g_ref[k] += gb[k] / B
+    gl = loss.cpu().numpy()
+    assert abs(gl.sum() - l_ref) < 2e-2 * l_ref
+    for k, gref in g_ref.items():
+        gg = net.grads[k].double().cpu().numpy()
+        if k == "enc0a.w":
+            gg, gref = gg[:, :2], gref[:, :2]          # padded input channels carry no signal
+        cos = float(np.sum(gg * gref) / (np.linalg.norm(gg) * np.linalg.norm(gref) + 1e-30))
+        print(f"{k}: rel {rel(gg, gref):.3e} cos {cos:.5f}", flush=True)
+        assert cos > 0.99 and rel(gg, gref) < 0.1, k
+
+
+def test_adam_matches_definition(env):
+    torch, nn, S = env
+    rng = np.random.default_rng(3)
+    p0, g = rng.standard_normal(1000), rng.standard_normal(1000)
+    p = torch.tensor(p0, dtype=torch.float32).cuda()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    gt = torch.tensor(g, dtype=torch.float32).cuda()
+    for step in (1, 2):
+        nn.adam(p, gt, m, v, 1e-2, 0.9, 0.999, 1e-8, step)
+    mm, vv, pp = np.zeros(1000), np.zeros(1000), p0.copy()
+    for step in (1, 2):
+        mm = 0.9 * mm + 0.1 * g
+        vv = 0.999 * vv + 0.001 * g * g
+        pp -= 1e-2 * (mm / (1 - 0.9 ** step)) / (np.sqrt(vv / (1 - 0.999 ** step)) + 1e-8)
+    np.testing.assert_allclose(p.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
