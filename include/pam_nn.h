@@ -73,13 +73,22 @@ pam_status_t pam_nn_upsample_backward(const void* dy, int32_t lddy, int32_t batc
                                       void* dx, int32_t lddx, void* hip_stream);
 
 /* Head: z_o = b[o] + sum_c feat[p][c] w[c][o] (w FP32 [c][2]); mask = sigmoid(z_0),
- * err = sigmoid(z_1).  With target (FP32 [pixels]) also the loss terms
- * loss[0] += sum |mask - t| / count, loss[1] += sum |err - |mask - t|| / count
- * (zero loss first) and dz (FP32 [pixels][2]) of their mean over `count` pixels,
- * the error target held constant.  target, dz and loss may be NULL (inference). */
+ * err = sigmoid(z_1).  With target t (FP32 [pixels]) also the weighted losses
+ * (zero loss[0..2] first):
+ *   loss[0] += sum_p w_p BCE(mask, t), loss[1] += sum_p w_p BCE(err, |mask - t|),
+ *   loss[2] += sum_p w_p |mask - t|   (reported, not differentiated),
+ * BCE(s, y) = -y log s - (1 - y) log(1 - s), and the gradient of loss[0] + loss[1]
+ * dz (FP32 [pixels][2]) = ((mask - t) w_p, (err - |mask - t|) w_p) with the error
+ * target held constant; w_p = weight[p] (FP32 [pixels]) or 1/count when weight
+ * is NULL.  target, weight, dz and loss may be NULL (inference). */
 pam_status_t pam_nn_head(const void* feat, int32_t c, int64_t pixels, const float* w, const float* b,
-                         const float* target, float* mask, float* err, float* dz, float* loss, int64_t count,
-                         void* hip_stream);
+                         const float* target, const float* weight, float* mask, float* err, float* dz, float* loss,
+                         int64_t count, void* hip_stream);
+
+/* Loss weights w[f][p] = ((1 - mix) E[f][p] / sum_p E[f][p] + mix / pixels) / batch:
+ * the loss concentrates where the image I = rho_n^2 E has energy. */
+pam_status_t pam_nn_loss_weights(const float* energy, int32_t batch, int64_t pixels, float mix, float* out,
+                                 void* hip_stream);
 
 /* Head gradients: dfeat (BF16 [pixels][c]) = dz w^T; dw (FP32 [c][2]) += feat^T dz;
  * db (FP32 [2]) += column sums of dz (zero dw, db first). */

@@ -15,7 +15,7 @@ Network (a U-Net): activations are NHWC arrays [H][W][C].
 Conventions: conv3x3 is a cross-correlation with zero padding,
   y[h, w, o] = b[o] + sum_{dh, dw in -1..1} sum_c x[h + dh, w + dw, c] * W[3 (dh + 1) + (dw + 1), c, o];
 maxpool passes the gradient to the first maximum in the order (0,0), (0,1), (1,0), (1,1);
-loss = mean |mask - t| + mean |err - stop(|mask - t|)| over pixels, sign(0) = 0.
+loss = sum_p w_p BCE(mask, t) + sum_p w_p BCE(err, stop(|mask - t|)) with w_p = 1/P by default.
 """
 from __future__ import annotations
 
@@ -132,16 +132,21 @@ def forward(p: Dict[str, np.ndarray], x: np.ndarray, levels: int):
     return sigmoid(z[..., 0]), sigmoid(z[..., 1]), cache
 
 
-def loss_and_grads(p: Dict[str, np.ndarray], x: np.ndarray, t: np.ndarray, levels: int, e_stop=None):
-    """Loss and gradients; the error target |mask - t| is a constant of the second term
-    (pass e_stop to hold it at given values, e.g. when differencing the loss)."""
+def loss_and_grads(p: Dict[str, np.ndarray], x: np.ndarray, t: np.ndarray, levels: int, e_stop=None, wts=None):
+    """Loss sum_p w_p BCE(mask, t) + sum_p w_p BCE(err, e) (w = 1/P unless given) and
+    gradients, BCE(s, y) = -y log s - (1 - y) log(1 - s) evaluated from the logits; the
+    error target e = |mask - t| is a constant of the second term (pass e_stop to hold it
+    at given values, e.g. when differencing the loss)."""
     mask, err, cache = forward(p, x, levels)
     P = t.size
+    w = np.full(t.shape, 1.0 / P) if wts is None else wts
     e = np.abs(mask - t) if e_stop is None else e_stop
-    loss = np.abs(mask - t).mean() + np.abs(err - e).mean()
+    z0, z1 = cache["z"][..., 0], cache["z"][..., 1]
+    sp = lambda v: np.logaddexp(0.0, v)           # softplus
+    loss = np.sum(w * (t * sp(-z0) + (1 - t) * sp(z0))) + np.sum(w * (e * sp(-z1) + (1 - e) * sp(z1)))
     dz = np.zeros(cache["z"].shape)
-    dz[..., 0] = np.sign(mask - t) * mask * (1 - mask) / P
-    dz[..., 1] = np.sign(err - e) * err * (1 - err) / P
+    dz[..., 0] = (mask - t) * w
+    dz[..., 1] = (err - e) * w
     g = {"head.w": np.einsum("hwc,hwo->co", cache["feat"], dz), "head.b": dz.sum(axis=(0, 1))}
     ch = [p[f"enc{l}b.w"].shape[2] for l in range(levels)]
     dskip = [None] * levels

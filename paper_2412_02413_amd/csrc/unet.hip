@@ -238,14 +238,15 @@ __global__ void upsample_bwd_kernel(const bf16* dy, int32_t lddy, int64_t n, int
 }
 
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + expf(-z)); }
-__device__ __forceinline__ float signf_(float v) { return (float)((v > 0.f) - (v < 0.f)); }
+__device__ __forceinline__ float softplusf_(float x) { return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x))); }
 
 __global__ __launch_bounds__(256) void head_kernel(const bf16* feat, int32_t c, int64_t P, const float* w,
-                                                   const float* b, const float* target, float* mask, float* err,
-                                                   float* dz, float* loss, float inv_count) {
-  __shared__ float red[2][256];
+                                                   const float* b, const float* target, const float* weight,
+                                                   float* mask, float* err, float* dz, float* loss,
+                                                   float inv_count) {
+  __shared__ float red[3][256];
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  float l0 = 0.f, l1 = 0.f;
+  float l0 = 0.f, l1 = 0.f, l2 = 0.f;
   if (p < P) {
     float z0 = b[0], z1 = b[1];
     for (int k = 0; k < c; ++k) {
@@ -257,31 +258,55 @@ __global__ __launch_bounds__(256) void head_kernel(const bf16* feat, int32_t c, 
     mask[p] = m;
     err[p] = e;
     if (target) {
-      const float d = m - target[p];
-      const float ae = fabsf(d);
-      l0 = ae;
-      l1 = fabsf(e - ae);
+      const float wp = weight ? weight[p] : inv_count;
+      const float t = target[p];
+      const float ae = fabsf(m - t);
+      // binary cross-entropy of sigmoid outputs: t softplus(-z) + (1 - t) softplus(z)
+      l0 = wp * (t * softplusf_(-z0) + (1.f - t) * softplusf_(z0));
+      l1 = wp * (ae * softplusf_(-z1) + (1.f - ae) * softplusf_(z1));
+      l2 = wp * ae;
       if (dz) {
-        dz[2 * p] = signf_(d) * m * (1.f - m) * inv_count;
-        dz[2 * p + 1] = signf_(e - ae) * e * (1.f - e) * inv_count;
+        dz[2 * p] = (m - t) * wp;
+        dz[2 * p + 1] = (e - ae) * wp;
       }
     }
   }
   if (!loss) return;  // grid-uniform
   red[0][threadIdx.x] = l0;
   red[1][threadIdx.x] = l1;
+  red[2][threadIdx.x] = l2;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       red[0][threadIdx.x] += red[0][threadIdx.x + s];
       red[1][threadIdx.x] += red[1][threadIdx.x + s];
+      red[2][threadIdx.x] += red[2][threadIdx.x + s];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(loss, red[0][0] * inv_count);
-    atomicAdd(loss + 1, red[1][0] * inv_count);
+    atomicAdd(loss, red[0][0]);
+    atomicAdd(loss + 1, red[1][0]);
+    atomicAdd(loss + 2, red[2][0]);
   }
+}
+
+// w[f][p] = ((1 - mix) E[f][p] / sum_p E[f][p] + mix / P) / batch
+__global__ __launch_bounds__(1024) void loss_weights_kernel(const float* E, int64_t P, float mix, float inv_batch,
+                                                            float* out) {
+  __shared__ float red[1024];
+  const int64_t f = blockIdx.x;
+  float s = 0.f;
+  for (int64_t p = threadIdx.x; p < P; p += 1024) s += E[f * P + p];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 512; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  const float inv = red[0] > 0.f ? (1.f - mix) / red[0] : 0.f;
+  const float u = (red[0] > 0.f ? mix : 1.f) / (float)P;
+  for (int64_t p = threadIdx.x; p < P; p += 1024) out[f * P + p] = (E[f * P + p] * inv + u) * inv_batch;
 }
 
 __global__ void head_dfeat_kernel(int32_t c, int64_t n, const float* w, const float* dz, bf16* dfeat) {
@@ -484,13 +509,21 @@ pam_status_t pam_nn_upsample_backward(const void* dy, int32_t lddy, int32_t batc
 }
 
 pam_status_t pam_nn_head(const void* feat, int32_t c, int64_t pixels, const float* w, const float* b,
-                         const float* target, float* mask, float* err, float* dz, float* loss, int64_t count,
-                         void* hip_stream) {
+                         const float* target, const float* weight, float* mask, float* err, float* dz, float* loss,
+                         int64_t count, void* hip_stream) {
   if (!feat || !w || !b || !mask || !err || c < 1 || pixels < 1 || count < 1 || ((dz || loss) && !target))
     return PAM_ERR_INVALID_ARG;
   hipLaunchKernelGGL(head_kernel, dim3(blocks_for(pixels, 256)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
-                     static_cast<const bf16*>(feat), c, pixels, w, b, target, mask, err, dz, loss,
+                     static_cast<const bf16*>(feat), c, pixels, w, b, target, weight, mask, err, dz, loss,
                      1.0f / (float)count);
+  return launched();
+}
+
+pam_status_t pam_nn_loss_weights(const float* energy, int32_t batch, int64_t pixels, float mix, float* out,
+                                 void* hip_stream) {
+  if (!energy || !out || batch < 1 || pixels < 1 || !(mix >= 0.f && mix <= 1.f)) return PAM_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(loss_weights_kernel, dim3(batch), dim3(1024), 0, static_cast<hipStream_t>(hip_stream), energy,
+                     pixels, mix, 1.0f / (float)batch, out);
   return launched();
 }
 

@@ -25,7 +25,8 @@ def lib():
             "pam_nn_maxpool_backward": [vp, i32, vp, i32, i32, i32, i32, vp, i32, i32, vp],
             "pam_nn_upsample": [vp, i32, i32, i32, i32, i32, vp, i32, vp],
             "pam_nn_upsample_backward": [vp, i32, i32, i32, i32, i32, vp, i32, vp],
-            "pam_nn_head": [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, i64, vp],
+            "pam_nn_head": [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp],
+            "pam_nn_loss_weights": [vp, i32, i64, f32, vp, vp],
             "pam_nn_head_backward": [vp, i32, i64, vp, vp, vp, vp, vp, vp],
             "pam_nn_adam": [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
             "pam_nn_pack_weights": [vp, i32, i32, vp, vp, vp],
@@ -85,9 +86,13 @@ def upsample_backward(dy, lddy, batch, h, w, c, dx, lddx, stream=None):
     _call("pam_nn_upsample_backward", _p(dy), lddy, batch, h, w, c, _p(dx), lddx, _s(stream))
 
 
-def head(feat, c, pixels, w, b, target, mask, err, dz, loss, count, stream=None):
-    _call("pam_nn_head", _p(feat), c, pixels, _p(w), _p(b), _p(target), _p(mask), _p(err), _p(dz), _p(loss), count,
-          _s(stream))
+def head(feat, c, pixels, w, b, target, weight, mask, err, dz, loss, count, stream=None):
+    _call("pam_nn_head", _p(feat), c, pixels, _p(w), _p(b), _p(target), _p(weight), _p(mask), _p(err), _p(dz),
+          _p(loss), count, _s(stream))
+
+
+def loss_weights(energy, batch, pixels, mix, out, stream=None):
+    _call("pam_nn_loss_weights", _p(energy), batch, pixels, mix, _p(out), _s(stream))
 
 
 def head_backward(feat, c, pixels, w, dz, dfeat, dw, db, stream=None):

@@ -151,8 +151,8 @@ class UNet:
         self.feat = h
         mask = self._buf("mask", (B, H, W), self.torch.float32)
         err = self._buf("err", (B, H, W), self.torch.float32)
-        nn.head(h, ch[0], B * H * W, self.params["head.w"], self.params["head.b"], None, mask, err, None, None,
-                B * H * W)
+        nn.head(h, ch[0], B * H * W, self.params["head.w"], self.params["head.b"], None, None, mask, err, None,
+                None, B * H * W)
         return mask, err
 
     def skip_view(self, l):
@@ -166,19 +166,21 @@ class UNet:
         return cat.view(-1)[ch[l + 1]:], ch[l + 1] + ch[l]
 
     # -- loss and backward -------------------------------------------------------------
-    def loss_backward(self, target):
-        """Head loss against target (FP32 [B][H][W]) and gradients of every parameter."""
+    def loss_backward(self, target, weight=None):
+        """Head loss against target (FP32 [B][H][W]) with optional per-pixel weights (FP32
+        [B][H][W]; default the mean over pixels) and gradients of every parameter."""
         torch = self.torch
         B, H, W = self.shape
         L, ch = self.levels, self.ch
         P0 = B * H * W
         mask, err = self.cache["mask"], self.cache["err"]
         dz = self._buf("dz", (P0, 2), torch.float32)
-        loss = self._buf("loss", (2,), torch.float32)
+        loss = self._buf("loss", (3,), torch.float32)   # BCE mask, BCE error head, weighted mask L1
         loss.zero_()
         for g in self.grads.values():
             g.zero_()
-        nn.head(self.feat, ch[0], P0, self.params["head.w"], self.params["head.b"], target, mask, err, dz, loss, P0)
+        nn.head(self.feat, ch[0], P0, self.params["head.w"], self.params["head.b"], target, weight, mask, err, dz,
+                loss, P0)
         d = self._buf("gdec0b", (B, H, W, ch[0]))
         nn.head_backward(self.feat, ch[0], P0, self.params["head.w"], dz, d, self.grads["head.w"],
                          self.grads["head.b"])
@@ -305,10 +307,14 @@ def build_dataset(seeds, geom, chunk: int = 64, workers: int = 16, log=None):
 # Training and inference
 # ----------------------------------------------------------------------------
 
-def train(net: UNet, E, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 0, log=None, log_every=50):
+def train(net: UNet, E, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 0, log=None, log_every=50,
+          mix: float = 0.1):
+    """Adam on batches drawn from (E, R); the loss weights each pixel by its share of the
+    frame's energy (blended with a uniform share `mix`), where the mask shapes the image."""
     torch = net.torch
     n, H, W = E.shape
     feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
+    wts = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
     rng = np.random.default_rng(seed)
     hist = []
     t0 = time.perf_counter()
@@ -317,14 +323,16 @@ def train(net: UNet, E, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: i
         e = E.index_select(0, idx).contiguous()
         r = R.index_select(0, idx).contiguous()
         nn.features(e, batch, H * W, feats)
+        nn.loss_weights(e, batch, H * W, mix, wts)
         net.forward(feats, batch, H, W)
-        loss = net.loss_backward(r)
+        loss = net.loss_backward(r, wts)
         net.adam_step(lr=lr)
         if it % log_every == 0 or it == steps - 1:
             l = loss.cpu().numpy()
-            hist.append((it, float(l[0]), float(l[1])))
+            hist.append((it, float(l[0]), float(l[1]), float(l[2])))
             if log:
-                log(f"step {it}: mask L1 {l[0]:.4f} err-head L1 {l[1]:.4f} ({time.perf_counter() - t0:.1f} s)")
+                log(f"step {it}: BCE mask {l[0]:.4f} BCE err {l[1]:.4f} weighted mask L1 {l[2]:.4f} "
+                    f"({time.perf_counter() - t0:.1f} s)")
     return hist
 
 
@@ -380,3 +388,126 @@ class SurrogatePipeline:
     def close(self):
         pam.pam_destroy(self.plan1)
         self.teacher.close()
+
+
+# ----------------------------------------------------------------------------
+# Evaluation (Section II-E metrics) and the training / evaluation driver
+# ----------------------------------------------------------------------------
+
+def image_metrics(I):
+    """ESA in pixels (area above half the maximum) and ISNR in dB (Eq. 12) per frame."""
+    torch = __import__("torch")
+    mx = I.flatten(1).max(dim=1).values[:, None, None]
+    inside = I > 0.5 * mx
+    n_in = inside.flatten(1).sum(1).double()
+    s_in = (I * inside).flatten(1).sum(1).double()
+    s_out = (I * ~inside).flatten(1).sum(1).double()
+    n_out = I[0].numel() - n_in
+    isnr = 10 * torch.log10((s_in / n_in) / (s_out / n_out).clamp_min(1e-300))
+    return n_in, isnr
+
+
+def compare(E, R, mask, label):
+    """Image error and metric differences of I = mask^2 E against AS-TAX's I = rho_n^2 E."""
+    torch = __import__("torch")
+    I_ref = R * R * E
+    I = mask * mask * E
+    rel = ((I - I_ref).flatten(1).norm(dim=1) / I_ref.flatten(1).norm(dim=1)).double()
+    esa_r, isnr_r = image_metrics(I_ref)
+    esa, isnr = image_metrics(I)
+    w = E / E.flatten(1).sum(1)[:, None, None]
+    ml1 = ((mask - R).abs() * w).flatten(1).sum(1).double()
+    return {"form": label, "image_rel_l2_mean": float(rel.mean()), "image_rel_l2_p95": float(rel.quantile(0.95)),
+            "mask_l1_energy_weighted_mean": float(ml1.mean()),
+            "mask_l1_mean": float((mask - R).abs().flatten(1).mean(1).mean()),
+            "abs_d_isnr_db_mean": float((isnr - isnr_r).abs().mean()),
+            "abs_d_esa_rel_mean": float(((esa - esa_r).abs() / esa_r).mean())}
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+    import torch
+    ap = argparse.ArgumentParser(description="train and evaluate the NCC-mask surrogate")
+    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--val", type=int, default=500)
+    ap.add_argument("--eval", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--base", type=int, default=32)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--fallback-rate", type=float, default=0.1, help="validation fallback fraction fixing tau")
+    ap.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    geom = synth.cfg4_geometry()
+    rep = {"geometry": "64 elements, 1024 samples at 20 MHz, 205 bins (1-5 MHz), 512 x 256 grid",
+           "network": f"U-Net {args.levels} levels, {args.base} base channels, BF16 operands, FP32 accumulation",
+           "train_frames": args.train, "val_frames": args.val, "eval_frames": args.eval, "steps": args.steps,
+           "batch": args.batch}
+    t0 = time.perf_counter()
+    E_tr, R_tr = build_dataset(list(range(args.train)), geom, workers=args.workers, log=log)
+    E_va, R_va = build_dataset(list(range(args.train, args.train + args.val)), geom, workers=args.workers)
+    E_ev, R_ev = build_dataset(list(range(1_000_000, 1_000_000 + args.eval)), geom, workers=args.workers)
+    rep["dataset_s"] = round(time.perf_counter() - t0, 1)
+    log(f"datasets in {rep['dataset_s']} s")
+    net = UNet(args.levels, args.base, seed=0)
+    t0 = time.perf_counter()
+    hist = train(net, E_tr, R_tr, args.steps, args.batch, args.lr, log=log, log_every=max(1, args.steps // 20))
+    torch.cuda.synchronize()
+    rep["train_s"] = round(time.perf_counter() - t0, 1)
+    rep["train_ms_per_step"] = round(1e3 * rep["train_s"] / max(1, args.steps), 2)
+    rep["loss_history"] = hist
+    # threshold from the validation split
+    _, _, conf_va = predict(net, E_va)
+    tau = float(torch.quantile(conf_va, args.fallback_rate)) if args.fallback_rate > 0 else -1.0
+    rep["tau"] = tau
+    # held-out evaluation
+    m_ev, e_ev, conf_ev = predict(net, E_ev)
+    fb = conf_ev < tau
+    m_fb = torch.where(fb[:, None, None], R_ev, m_ev)
+    ones = torch.ones_like(m_ev)
+    as3 = E_ev / E_ev.flatten(1).max(1).values[:, None, None]
+    rep["fallback_rate"] = float(fb.float().mean())
+    rep["results"] = [compare(E_ev, R_ev, m_fb, "surrogate with fallback"),
+                      compare(E_ev, R_ev, m_ev, "surrogate alone"),
+                      compare(E_ev, R_ev, ones, "plain AS (weight 1)"),
+                      compare(E_ev, R_ev, as3, "AS^3 self-mask (appendix)")]
+    # timing: surrogate pipeline (no fallback) vs plain AS-TAX on one 64-frame batch
+    rf = torch.from_numpy(generate_rf(list(range(2_000_000, 2_000_064)), args.workers)).cuda()
+    pipe = SurrogatePipeline(geom, net, tau=-1.0)
+    teacher = Teacher(geom)
+    try:
+        for _ in range(2):
+            pipe(rf)
+            teacher(rf)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            pipe(rf)
+        torch.cuda.synchronize()
+        t_s = (time.perf_counter() - t) / 5 / 64
+        t = time.perf_counter()
+        for _ in range(5):
+            teacher(rf)
+        torch.cuda.synchronize()
+        t_p = (time.perf_counter() - t) / 5 / 64
+    finally:
+        pipe.close()
+        teacher.close()
+    rep["ms_per_frame"] = {"surrogate (1 propagation + network)": round(1e3 * t_s, 4),
+                           "plain AS-TAX (3 propagations)": round(1e3 * t_p, 4)}
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        torch.save(net.state_dict(), args.out)
+    print(json.dumps(rep), flush=True)
+
+
+if __name__ == "__main__":
+    main()

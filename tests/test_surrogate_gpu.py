@@ -27,8 +27,8 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-30))
 
 
-@pytest.mark.parametrize("levels,H,W", [(2, 32, 64), (3, 32, 128)])
-def test_unet_forward_and_gradients_match_reference(env, levels, H, W):
+@pytest.mark.parametrize("levels,H,W,weighted", [(2, 32, 64, False), (3, 32, 128, False), (2, 32, 64, True)])
+def test_unet_forward_and_gradients_match_reference(env, levels, H, W, weighted):
     torch, nn, S = env
     B = 2
     net = S.UNet(levels=levels, base=32, seed=7)
@@ -44,8 +44,10 @@ def test_unet_forward_and_gradients_match_reference(env, levels, H, W):
     target = rng.uniform(0, 1, (B, H, W))
     x = torch.tensor(feats, dtype=torch.float32).to(torch.bfloat16).cuda()
     t = torch.tensor(target, dtype=torch.float32).cuda()
+    wts = rng.uniform(0, 1, (B, H, W))
+    wts /= wts.sum()
     mask, err = net.forward(x, B, H, W)
-    loss = net.loss_backward(t)
+    loss = net.loss_backward(t, torch.tensor(wts, dtype=torch.float32).cuda() if weighted else None)
     torch.cuda.synchronize()
     gm, ge = mask.cpu().numpy(), err.cpu().numpy()
     # reference with the BF16-rounded parameters the kernels use
@@ -56,12 +58,14 @@ def test_unet_forward_and_gradients_match_reference(env, levels, H, W):
     for b in range(B):
         m, e, _ = U.forward(ref_p, bf16_round(feats[b]), levels)
         assert rel(gm[b], m) < 2e-2 and rel(ge[b], e) < 2e-2
-        lb, gb, _ = U.loss_and_grads(ref_p, bf16_round(feats[b]), target[b], levels)
-        l_ref += lb / B
+        wb = wts[b] if weighted else None
+        lb, gb, _ = U.loss_and_grads(ref_p, bf16_round(feats[b]), target[b], levels, wts=wb)
+        scale = 1.0 if weighted else 1.0 / B
+        l_ref += lb * scale
         for k in gb:
-            g_ref[k] += gb[k] / B
+            g_ref[k] += gb[k] * scale
     gl = loss.cpu().numpy()
-    assert abs(gl.sum() - l_ref) < 2e-2 * l_ref
+    assert abs(gl[0] + gl[1] - l_ref) < 2e-2 * l_ref
     for k, gref in g_ref.items():
         gg = net.grads[k].double().cpu().numpy()
         if k == "enc0a.w":
@@ -87,3 +91,70 @@ def test_adam_matches_definition(env):
         vv = 0.999 * vv + 0.001 * g * g
         pp -= 1e-2 * (mm / (1 - 0.9 ** step)) / (np.sqrt(vv / (1 - 0.999 ** step)) + 1e-8)
     np.testing.assert_allclose(p.cpu().numpy(), pp, rtol=1e-5, atol=1e-6)
+
+
+@pytest.fixture(scope="module")
+def small_data(env):
+    torch, nn, S = env
+    from paper_2412_02413_amd import synth
+    g = synth.cfg4_geometry()
+    E, R = S.build_dataset(list(range(300)), g, workers=0)
+    E_ev, R_ev = S.build_dataset(list(range(1_000_000, 1_000_040)), g, workers=0)
+    return g, E, R, E_ev, R_ev
+
+
+def test_training_gains_over_plain_as(env, small_data):
+    """A short training run already brings the image much closer to AS-TAX than plain AS
+    (the method without the network: weight 1), and the training loss decreases."""
+    torch, nn, S = env
+    g, E, R, E_ev, R_ev = small_data
+    net = S.UNet(4, 32, seed=1)
+    hist = S.train(net, E, R, steps=300, batch=8, lr=3e-4, log_every=50)
+    first = np.mean([h[1] for h in hist[:2]])
+    last = np.mean([h[1] for h in hist[-2:]])
+    assert last < first
+    m, _, _ = S.predict(net, E_ev)
+    sur = S.compare(E_ev, R_ev, m, "surrogate")
+    plain = S.compare(E_ev, R_ev, torch.ones_like(m), "AS")
+    print(sur, plain, flush=True)
+    assert sur["image_rel_l2_mean"] < 0.3 * plain["image_rel_l2_mean"]
+    assert sur["abs_d_isnr_db_mean"] < 0.3 * plain["abs_d_isnr_db_mean"]
+
+
+def test_fallback_reproduces_plain_as_tax(env, small_data):
+    torch, nn, S = env
+    from paper_2412_02413_amd import pam, synth
+    g = synth.cfg4_geometry()
+    net = S.UNet(4, 32, seed=2)
+    rf = torch.from_numpy(S.generate_rf([5, 6, 7])).cuda()
+    pipe = S.SurrogatePipeline(g, net, tau=2.0)     # confidence never reaches 2: every frame falls back
+    try:
+        image, mask, conf, fb = pipe(rf)
+        assert fb.all()
+        plan = pam.pam_plan(g, 0)
+        try:
+            ref = pam.reconstruct(plan, rf)["image"]
+        finally:
+            pam.pam_destroy(plan)
+        torch.cuda.synchronize()
+        assert torch.equal(image, ref)
+    finally:
+        pipe.close()
+
+
+def test_checkpoint_round_trip(env, tmp_path):
+    torch, nn, S = env
+    net = S.UNet(3, 32, seed=4)
+    x = torch.rand((2, 64, 128, S.C_FEAT), device="cuda").to(torch.bfloat16)
+    t = torch.rand((2, 64, 128), device="cuda")
+    net.forward(x, 2, 64, 128)
+    net.loss_backward(t)
+    net.adam_step(1e-3)
+    path = tmp_path / "ck.pt"
+    torch.save(net.state_dict(), path)
+    other = S.UNet(3, 32, seed=9)
+    other.load_state_dict(torch.load(path, weights_only=True))
+    a, _ = net.forward(x, 2, 64, 128)
+    a = a.clone()
+    b, _ = other.forward(x, 2, 64, 128)
+    assert torch.equal(a, b) and other.step_count == net.step_count
