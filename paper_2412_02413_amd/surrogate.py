@@ -96,6 +96,17 @@ class UNet:
                 **{f"p.{k}": v for k, v in self.params.items()},
                 **{f"m.{k}": v for k, v in self.m.items()}, **{f"v.{k}": v for k, v in self.v.items()}}
 
+    @classmethod
+    def from_weights(cls, path, device: str = "cuda"):
+        """Network and threshold from an inference-weights file written by the driver."""
+        import torch
+        sd = torch.load(path, weights_only=True, map_location="cpu")
+        net = cls(int(sd["levels"]), int(sd["base"]), device=device)
+        for k in net.params:
+            net.params[k].copy_(sd[k])
+        net.pack()
+        return net, float(sd["tau"])
+
     def load_state_dict(self, sd):
         for k in self.params:
             self.params[k].copy_(sd[f"p.{k}"])
@@ -240,16 +251,26 @@ class UNet:
 # ----------------------------------------------------------------------------
 
 def _frame(seed):
+    """Training workload: 64-element array, 1-20 emitters, SNR uniform in [0, 30] dB."""
     return synth.cfg4_frame(seed)[0]
 
 
-def generate_rf(seeds: Sequence[int], workers: int = 0) -> np.ndarray:
+def _frame_headline(seed):
+    """Benchmark workload: 128-element array, 4096 samples, 3 stable + 2 inertial emitters."""
+    return synth.cfg2_frame(seed)[0]
+
+
+FRAME_KINDS = {"train": _frame, "headline": _frame_headline}
+
+
+def generate_rf(seeds: Sequence[int], workers: int = 0, kind: str = "train") -> np.ndarray:
+    fn = FRAME_KINDS[kind]
     if workers and len(seeds) > 32:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:
-            frames = pool.map(_frame, list(seeds), chunksize=16)
+            frames = pool.map(fn, list(seeds), chunksize=16)
     else:
-        frames = [_frame(s) for s in seeds]
+        frames = [fn(s) for s in seeds]
     return np.stack(frames)
 
 
@@ -282,14 +303,14 @@ class Teacher:
         pam.pam_destroy(self.plan)
 
 
-def build_dataset(seeds, geom, chunk: int = 64, workers: int = 16, log=None):
+def build_dataset(seeds, geom, chunk: int = 64, workers: int = 16, log=None, kind: str = "train"):
     """Energies and NNCC targets (FP32 device tensors [n][n_z][n_x]) of the given frames."""
     import torch
     t = Teacher(geom, max_frames=chunk)
     E, R = [], []
     try:
         for i in range(0, len(seeds), 512):
-            rf = generate_rf(seeds[i:i + 512], workers)
+            rf = generate_rf(seeds[i:i + 512], workers, kind)
             for j in range(0, rf.shape[0], chunk):
                 x = torch.from_numpy(rf[j:j + chunk]).cuda()
                 e, r, _ = t(x)
@@ -435,24 +456,34 @@ def main(argv=None):
     ap.add_argument("--eval", type=int, default=2000)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--base", type=int, default=32)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--fallback-rate", type=float, default=0.1, help="validation fallback fraction fixing tau")
-    ap.add_argument("--out", default="")
+    ap.add_argument("--headline-train", type=int, default=0,
+                    help="benchmark-workload frames (128 elements) added to the training set")
+    ap.add_argument("--headline-eval", type=int, default=64)
+    ap.add_argument("--out", default="", help="training checkpoint (parameters and Adam state)")
+    ap.add_argument("--weights", default="", help="inference weights (parameters and threshold)")
     args = ap.parse_args(argv)
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
     geom = synth.cfg4_geometry()
+    hgeom = synth.cfg2_geometry()
     rep = {"geometry": "64 elements, 1024 samples at 20 MHz, 205 bins (1-5 MHz), 512 x 256 grid",
            "network": f"U-Net {args.levels} levels, {args.base} base channels, BF16 operands, FP32 accumulation",
-           "train_frames": args.train, "val_frames": args.val, "eval_frames": args.eval, "steps": args.steps,
-           "batch": args.batch}
+           "train_frames": args.train, "headline_train_frames": args.headline_train, "val_frames": args.val,
+           "eval_frames": args.eval, "headline_eval_frames": args.headline_eval, "steps": args.steps,
+           "batch": args.batch, "lr": args.lr}
     t0 = time.perf_counter()
     E_tr, R_tr = build_dataset(list(range(args.train)), geom, workers=args.workers, log=log)
+    if args.headline_train:
+        Eh, Rh = build_dataset(list(range(3_000_000, 3_000_000 + args.headline_train)), hgeom,
+                               workers=args.workers, log=log, kind="headline")
+        E_tr, R_tr = torch.cat([E_tr, Eh]), torch.cat([R_tr, Rh])
     E_va, R_va = build_dataset(list(range(args.train, args.train + args.val)), geom, workers=args.workers)
     E_ev, R_ev = build_dataset(list(range(1_000_000, 1_000_000 + args.eval)), geom, workers=args.workers)
     rep["dataset_s"] = round(time.perf_counter() - t0, 1)
@@ -468,45 +499,73 @@ def main(argv=None):
     _, _, conf_va = predict(net, E_va)
     tau = float(torch.quantile(conf_va, args.fallback_rate)) if args.fallback_rate > 0 else -1.0
     rep["tau"] = tau
-    # held-out evaluation
-    m_ev, e_ev, conf_ev = predict(net, E_ev)
-    fb = conf_ev < tau
-    m_fb = torch.where(fb[:, None, None], R_ev, m_ev)
-    ones = torch.ones_like(m_ev)
-    as3 = E_ev / E_ev.flatten(1).max(1).values[:, None, None]
-    rep["fallback_rate"] = float(fb.float().mean())
-    rep["results"] = [compare(E_ev, R_ev, m_fb, "surrogate with fallback"),
-                      compare(E_ev, R_ev, m_ev, "surrogate alone"),
-                      compare(E_ev, R_ev, ones, "plain AS (weight 1)"),
-                      compare(E_ev, R_ev, as3, "AS^3 self-mask (appendix)")]
-    # timing: surrogate pipeline (no fallback) vs plain AS-TAX on one 64-frame batch
-    rf = torch.from_numpy(generate_rf(list(range(2_000_000, 2_000_064)), args.workers)).cuda()
-    pipe = SurrogatePipeline(geom, net, tau=-1.0)
-    teacher = Teacher(geom)
+    rep["heldout"] = evaluate(net, E_ev, R_ev, tau)
+    # the same network on the benchmark workload (128 elements, 768 bins, same grid)
+    rf_h = torch.from_numpy(generate_rf(list(range(4_000_000, 4_000_000 + args.headline_eval)), args.workers,
+                                        "headline")).cuda()
+    th = Teacher(hgeom, max_frames=64)
+    try:
+        Eh_ev, Rh_ev = [], []
+        for j in range(0, rf_h.shape[0], 64):
+            e, r, _ = th(rf_h[j:j + 64].contiguous())
+            Eh_ev.append(e)
+            Rh_ev.append(r)
+    finally:
+        torch.cuda.synchronize()
+        th.close()
+    rep["headline"] = evaluate(net, torch.cat(Eh_ev), torch.cat(Rh_ev), tau)
+    rep["ms_per_frame"] = {"train workload": timing(geom, net, generate_rf(list(range(2_000_000, 2_000_064)),
+                                                                             args.workers)),
+                           "benchmark workload": timing(hgeom, net, rf_h[:64].cpu().numpy())}
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        torch.save(net.state_dict(), args.out)
+    if args.weights:
+        os.makedirs(os.path.dirname(os.path.abspath(args.weights)), exist_ok=True)
+        torch.save({"levels": net.levels, "base": net.base, "tau": tau,
+                    **{k: v.cpu() for k, v in net.params.items()}}, args.weights)
+    print(json.dumps(rep), flush=True)
+
+
+def evaluate(net, E, R, tau):
+    import torch
+    m, _, conf = predict(net, E)
+    fb = conf < tau
+    m_fb = torch.where(fb[:, None, None], R, m)
+    as3 = E / E.flatten(1).max(1).values[:, None, None]
+    return {"frames": int(E.shape[0]), "fallback_rate": float(fb.float().mean()),
+            "results": [compare(E, R, m_fb, "surrogate with fallback"), compare(E, R, m, "surrogate alone"),
+                        compare(E, R, torch.ones_like(m), "plain AS (weight 1)"),
+                        compare(E, R, as3, "AS^3 self-mask (appendix)")]}
+
+
+def timing(geom, net, rf_host, reps: int = 5):
+    """ms per frame of the surrogate pipeline (no fallback) and of plain AS-TAX, 64-frame batches."""
+    import torch
+    rf = torch.from_numpy(np.ascontiguousarray(rf_host)).cuda()
+    F = rf.shape[0]
+    pipe = SurrogatePipeline(geom, net, tau=-1.0, max_frames=F)
+    teacher = Teacher(geom, max_frames=F)
     try:
         for _ in range(2):
             pipe(rf)
             teacher(rf)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(5):
+        for _ in range(reps):
             pipe(rf)
         torch.cuda.synchronize()
-        t_s = (time.perf_counter() - t) / 5 / 64
+        t_s = (time.perf_counter() - t) / reps / F
         t = time.perf_counter()
-        for _ in range(5):
+        for _ in range(reps):
             teacher(rf)
         torch.cuda.synchronize()
-        t_p = (time.perf_counter() - t) / 5 / 64
+        t_p = (time.perf_counter() - t) / reps / F
     finally:
         pipe.close()
         teacher.close()
-    rep["ms_per_frame"] = {"surrogate (1 propagation + network)": round(1e3 * t_s, 4),
-                           "plain AS-TAX (3 propagations)": round(1e3 * t_p, 4)}
-    if args.out:
-        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-        torch.save(net.state_dict(), args.out)
-    print(json.dumps(rep), flush=True)
+    return {"surrogate (1 propagation + network)": round(1e3 * t_s, 4),
+            "plain AS-TAX (3 propagations)": round(1e3 * t_p, 4)}
 
 
 if __name__ == "__main__":
