@@ -10,7 +10,10 @@ Prints ONE JSON line on stdout: throughput (frames/s), per-frame latency
 p50/p99 of single-frame calls, the dominant kernel's roofline figures measured
 live with HIP events on the library's stream, the error of the GPU result against
 the FP64 oracle on one frame, and the oracle itself timed on the host CPU
-(a reported baseline, not the target).  Diagnostics go to stderr.
+(a reported baseline, not the target).  Beside the main form: the other precision
+forms of the DFT-GEMM, and the NCC-mask surrogate (committed weights) on the same
+frames, with its fallback rate and its image against plain AS-TAX's.
+Diagnostics go to stderr.
 """
 from __future__ import annotations
 
@@ -82,6 +85,96 @@ def cpu_baseline(rf0: np.ndarray, geom):
                  "sample": f"1 full frame of the benchmark workload (seed 0): {dt:.1f} s"}
 
 
+def source_digest() -> str:
+    """SHA-256 of the fields kernel's sources: traffic counters stay valid only for this code."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("k3_fields.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2412_02413_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(precision: str):
+    """HBM bytes per launch of the fields kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None when the
+    summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "fields_traffic_cfg2_b64.txt")
+    if not os.path.exists(path):
+        return None
+    digest, vals = None, {}
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] == "source_sha256":
+                digest = parts[1]
+            elif parts and parts[0] == "traffic":
+                kv = dict(p.split("=", 1) for p in parts[2:])
+                vals[parts[1]] = int(kv["bytes_per_launch"])
+    if digest != source_digest():
+        return None
+    return vals.get(precision)
+
+
+def algorithmic_bytes(lay, n_frames: int, n_sel: int, geom) -> float:
+    """Bytes the fields kernel must move once per launch: the lateral coefficients of every
+    (frame, bin, sub-aperture) in, the accumulated energy and cross-spectra sums out."""
+    coeffs = n_frames * n_sel * geom.n_sub * geom.n_x * 8
+    accum = lay.n_split * n_frames * lay.n_acc * geom.n_z * geom.n_x * 4
+    return float(coeffs + accum)
+
+
+def copy_calibration(dev, mib: int = 1024, reps: int = 3):
+    """Plain device copies of a known size (outside any timed region): the per-dispatch
+    FETCH_SIZE / WRITE_SIZE counters of these copies scale the fields kernel's counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {reps} device copies of {mib} MiB")
+    del src, dst
+
+
+def surrogate_entry(geom, rf, plain_images, fps_plain, precision, steps, warmup, path):
+    """The NCC-mask surrogate (one full-aperture propagation + U-Net mask, confidence
+    fallback to plain AS-TAX) on the same frames: throughput, fallback rate, and its image
+    against plain AS-TAX's."""
+    import torch
+    from paper_2412_02413_amd import surrogate as S
+    net, tau = S.UNet.from_weights(path)
+    F = rf.shape[0]
+    pipe = S.SurrogatePipeline(geom, net, tau=tau, precision=precision, max_frames=F)
+    try:
+        for _ in range(warmup):
+            pipe(rf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fb = 0
+        for _ in range(steps):
+            image, _, _, fallback = pipe(rf)
+            fb += int(fallback.sum())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        pipe.close()
+    rel = ((image - plain_images).flatten(1).norm(dim=1) / plain_images.flatten(1).norm(dim=1)).double()
+    _, isnr_s = S.image_metrics(image)
+    _, isnr_p = S.image_metrics(plain_images)
+    fps = F * steps / wall
+    return {"frames_per_s": round(fps, 2), "ms_per_step": round(1e3 * wall / steps, 3),
+            "speedup_vs_plain": round(fps / fps_plain, 3), "tau": round(tau, 4),
+            "fallback_rate": round(fb / (F * steps), 4),
+            "image_rel_l2_vs_plain_mean": round(float(rel.mean()), 4),
+            "image_rel_l2_vs_plain_p95": round(float(rel.quantile(0.95)), 4),
+            "abs_d_isnr_db_mean": round(float((isnr_s - isnr_p).abs().mean()), 3),
+            "network": f"U-Net {net.levels} levels, {net.base} base channels, BF16 operands, FP32 accumulation",
+            "weights": os.path.relpath(path, ROOT)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +186,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="split_bf16,split_fp16,bf16,fp16",
                     help="other precision forms measured beside the main one (comma list, '' for none)")
+    ap.add_argument("--surrogate", default=os.path.join(ROOT, "paper_2412_02413_amd", "weights",
+                                                        "surrogate_l4_b32.safetensors"),
+                    help="surrogate weights measured beside plain AS-TAX ('' for none)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="finish with plain device copies of 1 GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); frames are independent, "
@@ -150,10 +248,11 @@ def main():
                     lat_wall.append(1e3 * (time.perf_counter() - tw))
                     lat_gpu.append(ev.elapsed_ms(e1[0], e1[-1]))
         n_sel = plan.info.n_bins
+        lay = pam.pam_workspace_layout(plan, F, geom.n_samples)
         pam.pam_destroy(plan)
         res = {"precision": precision, "ms_per_step": 1e3 * wall / args.steps,
                "frames_per_s": F * args.steps / wall, "stage_ms": stage_ms, "n_sel": n_sel,
-               "lat_gpu": lat_gpu, "lat_wall": lat_wall}
+               "lat_gpu": lat_gpu, "lat_wall": lat_wall, "layout": lay, "images": image}
         log(f"{precision}: {res['ms_per_step']:.2f} ms/step, {res['frames_per_s']:.1f} frames/s, "
             f"stages {stage_ms}")
         return res, image[0].cpu().numpy().astype(np.float64), nncc[0].cpu().numpy().astype(np.float64)
@@ -171,6 +270,8 @@ def main():
     achieved = flops / (k3_ms * 1e-3) / 1e12
     peak = MFMA_PEAK_TFLOPS[args.precision]
     alg = algorithmic_flops(geom, n_sel)
+    traffic = recorded_traffic(args.precision)
+    alg_bytes = algorithmic_bytes(main_res["layout"], F, n_sel, geom)
 
     # accuracy on frame 0 against the oracle, and the oracle's own speed on the host
     out = {}
@@ -185,6 +286,7 @@ def main():
     variants = {}
     for prec in [v for v in args.variants.split(",") if v and v != args.precision]:
         r, im, rh = measure(prec, 0)
+        del r["images"]
         k3v = r["stage_ms"]["fields"]
         fl = executed_mfma_flops(geom, r["n_sel"], F, prec)
         variants[prec] = {"frames_per_s": round(r["frames_per_s"], 2), "ms_per_step": round(r["ms_per_step"], 3),
@@ -192,6 +294,17 @@ def main():
                           "fields_ms": round(k3v, 3),
                           "mfma_tflops": round(fl / (k3v * 1e-3) / 1e12, 2), "mfma_peak": MFMA_PEAK_TFLOPS[prec],
                           "error_vs_oracle": err(im, rh, ref) if ref is not None else None}
+
+    sur = None
+    if args.surrogate:
+        if os.path.exists(args.surrogate):
+            sur = surrogate_entry(geom, rf, main_res["images"], fps, args.precision, args.steps, args.warmup,
+                                  args.surrogate)
+            log(f"surrogate: {sur}")
+        else:
+            log(f"surrogate weights not found at {args.surrogate}: no surrogate entry")
+    if args.copy_calibration:
+        copy_calibration(dev)
 
     rec = {
         "metric": METRIC,
@@ -216,12 +329,14 @@ def main():
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": {"kernel": "fields (propagate + DFT-GEMM + cross-spectra)", "bound": "mfma",
                      "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "flops_per_launch": flops},
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "flops_per_launch": flops, "algorithmic_bytes_per_launch": alg_bytes,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
         "algorithmic_gflop_per_frame": round(alg / 1e9, 3),
         "algorithmic_tflops": round(alg * fps / 1e12, 3),
         "cpu_baseline": cpu,
         "variants": variants,
+        "surrogate": sur,
     }
     rec.update(out)
     ev.close()

@@ -99,13 +99,19 @@ class UNet:
     @classmethod
     def from_weights(cls, path, device: str = "cuda"):
         """Network and threshold from an inference-weights file written by the driver."""
-        import torch
-        sd = torch.load(path, weights_only=True, map_location="cpu")
-        net = cls(int(sd["levels"]), int(sd["base"]), device=device)
-        for k in net.params:
-            net.params[k].copy_(sd[k])
+        from safetensors import safe_open
+        with safe_open(path, framework="pt") as f:
+            meta = f.metadata()
+            net = cls(int(meta["levels"]), int(meta["base"]), device=device)
+            for k in net.params:
+                net.params[k].copy_(f.get_tensor(k))
         net.pack()
-        return net, float(sd["tau"])
+        return net, float(meta["tau"])
+
+    def save_weights(self, path, tau: float):
+        from safetensors.torch import save_file
+        save_file({k: v.detach().cpu().contiguous() for k, v in self.params.items()}, path,
+                  metadata={"levels": str(self.levels), "base": str(self.base), "tau": repr(float(tau))})
 
     def load_state_dict(self, sd):
         for k in self.params:
@@ -465,7 +471,7 @@ def main(argv=None):
                     help="benchmark-workload frames (128 elements) added to the training set")
     ap.add_argument("--headline-eval", type=int, default=64)
     ap.add_argument("--out", default="", help="training checkpoint (parameters and Adam state)")
-    ap.add_argument("--weights", default="", help="inference weights (parameters and threshold)")
+    ap.add_argument("--weights", default="", help="inference weights (parameters and threshold, safetensors)")
     args = ap.parse_args(argv)
 
     def log(*a):
@@ -522,8 +528,7 @@ def main(argv=None):
         torch.save(net.state_dict(), args.out)
     if args.weights:
         os.makedirs(os.path.dirname(os.path.abspath(args.weights)), exist_ok=True)
-        torch.save({"levels": net.levels, "base": net.base, "tau": tau,
-                    **{k: v.cpu() for k, v in net.params.items()}}, args.weights)
+        net.save_weights(args.weights, tau)
     print(json.dumps(rep), flush=True)
 
 
