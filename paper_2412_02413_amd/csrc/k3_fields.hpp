@@ -61,7 +61,7 @@ template <int NSUB, int GEN, typename BT, int CPY>
 __device__ __forceinline__ void load_gen_inputs(const K3Args& a, int f, int b, int q0, int ptid, int npt,
                                                 StageIn<NSUB, GEN, BT, CPY>& in) {
   const int N = a.N;
-  const double* kzb = a.kz + (size_t)a.sel[b] * (N / 2 + 1);
+  const double* kzb = a.kz + (size_t)b * (N / 2 + 1);
   in.kz_half = kzb[N / 2];
   const float2* g = a.coeffs + ((size_t)f * a.n_sel + b) * NSUB * N;
 #pragma unroll
@@ -222,21 +222,32 @@ __global__ __launch_bounds__(NC * 128, 1) void k3_fields_fp32(K3Args a) {
 #pragma unroll
       for (int k = 0; k < CPY; ++k) Bb[ptid + k * NPT] = in.bc[k];
     };
-    // inputs of stage s+2 are in flight while stage s+1 is generated
+    // inputs of stage s+2 are in flight while stage s+1 is generated; the two
+    // input sets swap roles every stage (no register copies, so no wait on loads
+    // still in flight)
     if (S > 0) {
       load(0, cur);
       store(0, cur, Abuf, reinterpret_cast<float4*>(Bbuf));
     }
     if (S > 1) load(1, cur);
     __syncthreads();
-    for (int s = 0; s < S; ++s) {
-      if (s + 1 < S) {
-        if (s + 2 < S) load(s + 2, nxt);
-        store(s + 1, cur, Abuf + ((s + 1) & 1) * A_SZ, reinterpret_cast<float4*>(Bbuf + ((s + 1) & 1) * B_SZ));
-        cur = nxt;
-      }
+    // Loads are unconditional (the last stage's inputs are re-read past the end) so
+    // the in-flight registers never merge with older values at a branch.
+    auto step = [&](int s, StageIn<NSUB, GEN, float4, CPY>& gen, StageIn<NSUB, GEN, float4, CPY>& fill) {
+      load(min(s + 2, S - 1), fill);
+      store(s + 1, gen, Abuf + ((s + 1) & 1) * A_SZ, reinterpret_cast<float4*>(Bbuf + ((s + 1) & 1) * B_SZ));
       __syncthreads();
+    };
+    int s = 0;
+    for (; s + 2 < S; s += 2) {
+      step(s, cur, nxt);
+      step(s + 1, nxt, cur);
     }
+    if (s + 1 < S) {
+      step(s, cur, nxt);
+      ++s;
+    }
+    if (S > 0) __syncthreads();   // stage S-1: nothing left to generate
     return;
   }
 
@@ -374,21 +385,31 @@ __global__ __launch_bounds__(NC * 128, 1) void k3_fields_split(K3Args a) {
 #pragma unroll
       for (int k = 0; k < CPY; ++k) *reinterpret_cast<v8*>(Bb + copy_off(k)) = in.bc[k];
     };
-    // inputs of stage s+2 are in flight while stage s+1 is generated
+    // inputs of stage s+2 are in flight while stage s+1 is generated (ping-pong
+    // input sets, as in the FP32 kernel)
     if (S > 0) {
       load(0, cur);
       store(0, cur, Abuf, Bbuf);
     }
     if (S > 1) load(1, cur);
     __syncthreads();
-    for (int s = 0; s < S; ++s) {
-      if (s + 1 < S) {
-        if (s + 2 < S) load(s + 2, nxt);
-        store(s + 1, cur, Abuf + ((s + 1) & 1) * A_SZ, Bbuf + ((s + 1) & 1) * B_SZ);
-        cur = nxt;
-      }
+    // Loads are unconditional (the last stage's inputs are re-read past the end) so
+    // the in-flight registers never merge with older values at a branch.
+    auto step = [&](int s, StageIn<NSUB, GEN, v8, CPY>& gen, StageIn<NSUB, GEN, v8, CPY>& fill) {
+      load(min(s + 2, S - 1), fill);
+      store(s + 1, gen, Abuf + ((s + 1) & 1) * A_SZ, Bbuf + ((s + 1) & 1) * B_SZ);
       __syncthreads();
+    };
+    int s = 0;
+    for (; s + 2 < S; s += 2) {
+      step(s, cur, nxt);
+      step(s + 1, nxt, cur);
     }
+    if (s + 1 < S) {
+      step(s, cur, nxt);
+      ++s;
+    }
+    if (S > 0) __syncthreads();   // stage S-1: nothing left to generate
     return;
   }
 

@@ -209,9 +209,8 @@ __global__ __launch_bounds__(256) void k2_lateral(K2Args a) {
 struct K3Args {
   const float2* coeffs;    // [F][n_sel][n_sub][N] slot order
   const float* inv_scale;  // [F][n_sel]
-  const double* kz;        // [n_bins_plan][N/2 + 1] signed kz / (2 pi), cycles per metre
+  const double* kz;        // [n_sel][N/2 + 1] signed kz / (2 pi) of the selected bins, cycles per metre
   const double* z;         // [n_z]
-  const int32_t* sel;      // [n_sel] plan bin index of each selected bin
   const float* basis;      // [N][N] slot-major fixed real basis (FP32 kernel)
   const void* basis_hi;    // [N x][N slots] transposed basis, 16-bit hi part (split kernels)
   const void* basis_lo;    // [N x][N slots] transposed basis, 16-bit lo part

@@ -38,8 +38,8 @@ struct Level {
   int n_t = 0;
   int stride = 1;        // 2^j
   int n_sel = 0;
-  int32_t* d_sel = nullptr;   // plan bin index of each selected bin
   int32_t* d_ksel = nullptr;  // bin k on the level's own grid
+  double* d_kz = nullptr;     // [n_sel][N/2+1] signed kz / (2 pi) of the selected bins
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -89,7 +89,6 @@ struct pam_plan_s {
   std::vector<int32_t> bins;  // k on the plan grid
   std::vector<Level> levels;
   // device tables
-  double* d_kz = nullptr;      // [n_bins][N/2+1] signed kz / (2 pi)
   double* d_z = nullptr;       // [n_z]
   float2* d_tw = nullptr;      // [n_t/2] time-FFT twiddles
   float2* d_twx = nullptr;     // [N] lateral DFT twiddles
@@ -385,7 +384,6 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
   }
 
   do {
-    if ((st = upload(p, &p->d_kz, kz.data(), kz.size())) != PAM_OK) break;
     if (is_split(p->precision)) {
       if ((st = upload(p, &p->d_bhi, bhi.data(), bhi.size())) != PAM_OK) break;
       if ((st = upload(p, &p->d_blo, blo.data(), blo.size())) != PAM_OK) break;
@@ -400,15 +398,16 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       Level lv;
       lv.n_t = p->n_t / stride;
       lv.stride = stride;
-      std::vector<int32_t> sel, ksel;
+      std::vector<int32_t> ksel;
+      std::vector<double> kz_lv;
       for (int b = 0; b < p->n_bins; ++b)
         if (ks[b] % stride == 0) {
-          sel.push_back(b);
           ksel.push_back(ks[b] / stride);
+          kz_lv.insert(kz_lv.end(), kz.begin() + (size_t)b * HQ, kz.begin() + (size_t)(b + 1) * HQ);
         }
-      lv.n_sel = (int)sel.size();
-      if ((st = upload(p, &lv.d_sel, sel.data(), sel.size())) != PAM_OK) break;
+      lv.n_sel = (int)ksel.size();
       if ((st = upload(p, &lv.d_ksel, ksel.data(), ksel.size())) != PAM_OK) break;
+      if ((st = upload(p, &lv.d_kz, kz_lv.data(), kz_lv.size())) != PAM_OK) break;
       p->levels.push_back(lv);
     }
   } while (false);
@@ -508,7 +507,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   // K3: fused propagate / inverse lateral transform / cross-spectra
   {
     const LaunchShape s = k3_shape(p, F, lv->n_sel);
-    pam::K3Args a{coeffs, scales, p->d_kz, p->d_z, lv->d_sel, p->d_basis, p->d_bhi, p->d_blo, accum,
+    pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, accum,
                   p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
     if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
