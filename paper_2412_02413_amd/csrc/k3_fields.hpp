@@ -61,7 +61,7 @@ template <int NSUB, int GEN, typename BT, int CPY>
 __device__ __forceinline__ void load_gen_inputs(const K3Args& a, int f, int b, int q0, int ptid, int npt,
                                                 StageIn<NSUB, GEN, BT, CPY>& in) {
   const int N = a.N;
-  const double* kzb = a.kz + (size_t)b * (N / 2 + 1);
+  const double* kzb = a.kz + (size_t)b * kz_row(N);
   in.kz_half = kzb[N / 2];
   const float2* g = a.coeffs + ((size_t)f * a.n_sel + b) * NSUB * N;
 #pragma unroll
@@ -293,6 +293,78 @@ __global__ __launch_bounds__(NC * 128, 1) void k3_fields_fp32(K3Args a) {
   store_acc<NSUB, 1>(a, sp, f, d0, xwg + w * 32, lane, accS, accC);
 }
 
+// Generation items of the 16-bit kernels: four consecutive slots (two slot
+// pairs) of one row, so each A plane is written with one 8-byte LDS store per
+// item.  Item e: slot quad p4 = (e & 1) | ((e >> 6) << 1), row r = (e >> 1) & 31.
+// Within 16 lanes this covers 8 rows x 2 quads, whose 8-byte stores fall in
+// distinct banks for the 80-byte row pitch.
+struct QuadItem {
+  int r, p4;
+  __device__ QuadItem(int e) : r((e >> 1) & 31), p4((e & 1) | ((e >> 6) << 1)) {}
+};
+
+template <int NSUB, int GENQ, typename BT, int CPY>
+struct QuadIn {
+  double2 kz[GENQ];        // kz / (2 pi) at q and q + 1
+  double kz_half;
+  float4 g[GENQ][NSUB][2];  // coefficients of the quad's four slots
+  BT bc[CPY];
+};
+
+template <int NSUB, int GENQ, typename BT, int CPY>
+__device__ __forceinline__ void load_quad_inputs(const K3Args& a, int f, int b, int q0, int ptid, int npt,
+                                                 QuadIn<NSUB, GENQ, BT, CPY>& in) {
+  const int N = a.N;
+  const double* kzb = a.kz + (size_t)b * kz_row(N);   // even row pitch: 16-byte aligned pairs
+  in.kz_half = kzb[N / 2];
+  const float2* g = a.coeffs + ((size_t)f * a.n_sel + b) * NSUB * N;
+#pragma unroll
+  for (int k = 0; k < GENQ; ++k) {
+    const QuadItem it(ptid + k * npt);
+    const int q = q0 + 2 * it.p4;            // q0 even, so q is even: 16-byte aligned pair
+    in.kz[k] = *reinterpret_cast<const double2*>(kzb + q);
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) {
+      const float4* gp = reinterpret_cast<const float4*>(g + (size_t)i * N + 2 * q);
+      in.g[k][i][0] = gp[0];
+      in.g[k][i][1] = gp[1];
+    }
+  }
+}
+
+// A values of quad item k: vals[t][j] = A_t[r, 4 p4 + j] for every tile t.
+template <int NSUB, int GENQ, typename BT, int CPY>
+__device__ __forceinline__ void gen_quad(const K3Args& a, double z, const QuadIn<NSUB, GENQ, BT, CPY>& in, int k,
+                                         bool q_is_zero, float vals[2 * NSUB][4]) {
+  float2 h0 = make_float2(0.f, 0.f), h1 = h0, h2 = h0;
+  if (z >= 0.0) {
+    h0 = propagator(z, in.kz[k].x, a.zero_evanescent);
+    h1 = q_is_zero ? propagator(z, in.kz_half, a.zero_evanescent) : h0;
+    h2 = propagator(z, in.kz[k].y, a.zero_evanescent);
+  }
+#pragma unroll
+  for (int i = 0; i < NSUB; ++i) {
+    const float4 g0 = in.g[k][i][0], g1 = in.g[k][i][1];
+    const float2 a0 = cmul(h0, make_float2(g0.x, g0.y));
+    const float2 a1 = cmul(h1, make_float2(g0.z, g0.w));
+    const float2 a2 = cmul(h2, make_float2(g1.x, g1.y));
+    const float2 a3 = cmul(h2, make_float2(g1.z, g1.w));
+    vals[2 * i][0] = a0.x;
+    vals[2 * i][1] = a1.x;
+    vals[2 * i][2] = a2.x;
+    vals[2 * i][3] = a3.x;
+    vals[2 * i + 1][0] = a0.y;
+    vals[2 * i + 1][1] = a1.y;
+    vals[2 * i + 1][2] = a2.y;
+    vals[2 * i + 1][3] = a3.y;
+  }
+}
+
+template <typename T>
+struct alignas(8) Quad16 {
+  T v[4];
+};
+
 // 16-bit operands on v_mfma_f32_32x32x16_{bf16,f16} (K = 16 slots per
 // instruction).  Operands are split x = hi + lo (hi = round16(x),
 // lo = round16(x - hi)); PASSES = 3 accumulates hi*hi + hi*lo + lo*hi in FP32
@@ -313,9 +385,9 @@ __global__ __launch_bounds__(NC * 128, 1) void k3_fields_split(K3Args a) {
   constexpr int NH = PASSES == 3 ? 2 : 1;   // hi (and lo) planes
   constexpr int A_SZ = NT * NH * 32 * RS;   // elements
   constexpr int B_SZ = NH * WC * RS;
-  constexpr int GEN = 32 * (KC / 2) / NPT;
+  constexpr int GENQ = 32 * (KC / 4) / NPT;         // quad items per producer thread per stage
   constexpr int CPY = (NH * WC * (KC / 8)) / NPT;   // 16-byte basis copies per producer thread
-  static_assert(GEN >= 1 && (32 * (KC / 2)) % NPT == 0, "generation split");
+  static_assert(GENQ >= 1 && (32 * (KC / 4)) % NPT == 0, "generation split");
   static_assert(CPY >= 1 && (NH * WC * (KC / 8)) % NPT == 0, "basis copy split");
   extern __shared__ float smem[];
   T* Abuf = reinterpret_cast<T*>(smem);     // [2][A_SZ]
@@ -338,52 +410,59 @@ __global__ __launch_bounds__(NC * 128, 1) void k3_fields_split(K3Args a) {
   if (w >= NC) {
     // ---------------- producer ----------------
     const int ptid = tid - NC * 64;
-    const GenRows<GEN> rows(a, ptid, NPT, d0);
-    StageIn<NSUB, GEN, v8, CPY> cur, nxt;
-    // basis copy item e: plane hl (hi, lo), column xc, 8-slot group g8
-    auto copy_off = [&](int k) {
+    double zr[GENQ];
+#pragma unroll
+    for (int k = 0; k < GENQ; ++k) {
+      const int d = d0 + QuadItem(ptid + k * NPT).r;
+      zr[k] = d < a.n_z ? a.z[d] : -1.0;
+    }
+    QuadIn<NSUB, GENQ, v8, CPY> cur, nxt;
+    // basis copy item e: column xc (fastest, so 8 lanes of one 16-byte store
+    // group hit 8 distinct bank groups for the 80-byte pitch), 8-slot group g8, plane hl
+    auto copy_item = [&](int k, int& xc, int& g8, int& hl) {
       const int e = ptid + k * NPT;
-      const int g8 = e % (KC / 8);
-      const int rest = e / (KC / 8);
-      const int xc = rest % WC, hl = rest / WC;
-      return (hl * WC + xc) * RS + 8 * g8;
+      xc = e % WC;
+      const int rest = e / WC;
+      g8 = rest % (KC / 8);
+      hl = rest / (KC / 8);
     };
-    auto load = [&](int s, StageIn<NSUB, GEN, v8, CPY>& in) {
+    auto load = [&](int s, QuadIn<NSUB, GENQ, v8, CPY>& in) {
       const int c = sm.chunk(s);
-      load_gen_inputs<NSUB, GEN>(a, f, sm.bin(s), c * (KC / 2), ptid, NPT, in);
+      load_quad_inputs<NSUB, GENQ>(a, f, sm.bin(s), c * (KC / 2), ptid, NPT, in);
 #pragma unroll
       for (int k = 0; k < CPY; ++k) {
-        const int e = ptid + k * NPT;
-        const int g8 = e % (KC / 8);
-        const int rest = e / (KC / 8);
-        const int xc = rest % WC, hl = rest / WC;
+        int xc, g8, hl;
+        copy_item(k, xc, g8, hl);
         const T* src = reinterpret_cast<const T*>(hl ? a.basis_lo : a.basis_hi);
-        in.bc[k] = *reinterpret_cast<const v8*>(src + (size_t)(xwg + xc) * N + c * KC + 8 * g8);
+        in.bc[k] = *reinterpret_cast<const v8*>(src + ((size_t)(c * (KC / 8) + g8) * N + xwg + xc) * 8);
       }
     };
-    auto store = [&](int s, const StageIn<NSUB, GEN, v8, CPY>& in, T* Ab, T* Bb) {
+    auto store = [&](int s, const QuadIn<NSUB, GENQ, v8, CPY>& in, T* Ab, T* Bb) {
       const int c0q = sm.chunk(s) * (KC / 2);
 #pragma unroll
-      for (int k = 0; k < GEN; ++k) {
-        const int e = ptid + k * NPT;
-        const int r = e & 31, ql = e >> 5;
-        float vals[NT][2];
-        gen_values<NSUB>(a, rows.z[k], in, k, c0q + ql == 0, vals);
+      for (int k = 0; k < GENQ; ++k) {
+        const QuadItem it(ptid + k * NPT);
+        float vals[NT][4];
+        gen_quad<NSUB>(a, zr[k], in, k, c0q + 2 * it.p4 == 0, vals);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          Pair16<T> hi, lo;
-          hi.x = (T)vals[t][0];
-          hi.y = (T)vals[t][1];
-          *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 0) * 32 + r) * RS + 2 * ql) = hi;
+          Quad16<T> hi, lo;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) hi.v[j] = (T)vals[t][j];
+          *reinterpret_cast<Quad16<T>*>(Ab + ((t * NH + 0) * 32 + it.r) * RS + 4 * it.p4) = hi;
           if (NH == 2) {
-            lo.x = (T)(vals[t][0] - (float)hi.x);
-            lo.y = (T)(vals[t][1] - (float)hi.y);
-            *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 1) * 32 + r) * RS + 2 * ql) = lo;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lo.v[j] = (T)(vals[t][j] - (float)hi.v[j]);
+            *reinterpret_cast<Quad16<T>*>(Ab + ((t * NH + 1) * 32 + it.r) * RS + 4 * it.p4) = lo;
           }
         }
       }
 #pragma unroll
-      for (int k = 0; k < CPY; ++k) *reinterpret_cast<v8*>(Bb + copy_off(k)) = in.bc[k];
+      for (int k = 0; k < CPY; ++k) {
+        int xc, g8, hl;
+        copy_item(k, xc, g8, hl);
+        *reinterpret_cast<v8*>(Bb + (hl * WC + xc) * RS + 8 * g8) = in.bc[k];
+      }
     };
     // inputs of stage s+2 are in flight while stage s+1 is generated (ping-pong
     // input sets, as in the FP32 kernel)
@@ -395,7 +474,7 @@ __global__ __launch_bounds__(NC * 128, 1) void k3_fields_split(K3Args a) {
     __syncthreads();
     // Loads are unconditional (the last stage's inputs are re-read past the end) so
     // the in-flight registers never merge with older values at a branch.
-    auto step = [&](int s, StageIn<NSUB, GEN, v8, CPY>& gen, StageIn<NSUB, GEN, v8, CPY>& fill) {
+    auto step = [&](int s, QuadIn<NSUB, GENQ, v8, CPY>& gen, QuadIn<NSUB, GENQ, v8, CPY>& fill) {
       load(min(s + 2, S - 1), fill);
       store(s + 1, gen, Abuf + ((s + 1) & 1) * A_SZ, Bbuf + ((s + 1) & 1) * B_SZ);
       __syncthreads();

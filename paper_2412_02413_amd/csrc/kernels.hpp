@@ -33,6 +33,9 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr double kTwoPiHi = 6.283185307179586232;      // 2 pi rounded to FP64
 
+// Row pitch of the kz tables: N/2 + 1 values padded to an even count.
+__host__ __device__ constexpr int kz_row(int N) { return N / 2 + 2; }
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -209,11 +212,11 @@ __global__ __launch_bounds__(256) void k2_lateral(K2Args a) {
 struct K3Args {
   const float2* coeffs;    // [F][n_sel][n_sub][N] slot order
   const float* inv_scale;  // [F][n_sel]
-  const double* kz;        // [n_sel][N/2 + 1] signed kz / (2 pi) of the selected bins, cycles per metre
+  const double* kz;        // [n_sel][kz_row(N)] signed kz / (2 pi) of the selected bins at q = 0..N/2, cycles per metre
   const double* z;         // [n_z]
   const float* basis;      // [N][N] slot-major fixed real basis (FP32 kernel)
-  const void* basis_hi;    // [N x][N slots] transposed basis, 16-bit hi part (split kernels)
-  const void* basis_lo;    // [N x][N slots] transposed basis, 16-bit lo part
+  const void* basis_hi;    // [N/8 slot groups][N x][8 slots] basis, 16-bit hi part (split kernels)
+  const void* basis_lo;    // same layout, 16-bit lo part
   float* accum;            // [n_split][F][n_acc][n_z][N]
   int32_t N, n_z, n_sel, F, n_dt, n_xg, n_split, bins_per_split, zero_evanescent;
 };

@@ -12,6 +12,7 @@
 #include "../../include/pam.h"
 #include "kernels.hpp"
 #include "k3_fields.hpp"
+#include "k3_fields16.hpp"
 
 namespace {
 
@@ -39,7 +40,7 @@ struct Level {
   int stride = 1;        // 2^j
   int n_sel = 0;
   int32_t* d_ksel = nullptr;  // bin k on the level's own grid
-  double* d_kz = nullptr;     // [n_sel][N/2+1] signed kz / (2 pi) of the selected bins
+  double* d_kz = nullptr;     // [n_sel][kz_row(N)] signed kz / (2 pi) of the selected bins
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -95,8 +96,8 @@ struct pam_plan_s {
   float* d_masks = nullptr;    // [n_sub][L]
   int32_t col0 = 0, col_step = 1;  // grid column of element l: col0 + col_step * l
   float* d_basis = nullptr;    // [N][N] slot-major cos/sin basis (FP32 kernel)
-  uint16_t* d_bhi = nullptr;   // [N][N] transposed basis, 16-bit hi (split kernels)
-  uint16_t* d_blo = nullptr;   // [N][N] transposed basis, 16-bit lo
+  uint16_t* d_bhi = nullptr;   // [N/8][N][8] basis (slot groups, x, slots), 16-bit hi (split kernels)
+  uint16_t* d_blo = nullptr;   // same layout, 16-bit lo
   std::vector<void*> allocs;
 };
 
@@ -168,16 +169,26 @@ std::vector<int32_t> select_bins(const pam_geometry_t* g) {
 
 struct LaunchShape {
   int n_dt, nw, xt, n_xg, n_split, bins_per_split;
+  int ct;   // > 0: 16-depth kernels with ct 16-column tiles per consumer wave
 };
 
 LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
   LaunchShape s;
-  s.n_dt = (p->n_z + 31) / 32;
-  const int tiles = p->N / 32;
-  s.nw = (tiles % 4 == 0) ? 4 : (tiles % 2 == 0 ? 2 : 1);
-  // nw consumer waves (one 32-column tile each) and as many producer waves
   s.xt = 1;
-  s.n_xg = p->N / (32 * s.nw * s.xt);
+  if (p->N % 64 == 0) {
+    // 16 depths x 64 ct columns per workgroup (4 consumer + 4 producer waves)
+    s.ct = p->N % 256 == 0 ? 4 : (p->N % 128 == 0 ? 2 : 1);
+    s.nw = 4;
+    s.n_dt = (p->n_z + 15) / 16;
+    s.n_xg = p->N / (64 * s.ct);
+  } else {
+    // 32 depths x 32 nw columns per workgroup (nw consumer + nw producer waves)
+    s.ct = 0;
+    s.n_dt = (p->n_z + 31) / 32;
+    const int tiles = p->N / 32;
+    s.nw = (tiles % 4 == 0) ? 4 : (tiles % 2 == 0 ? 2 : 1);
+    s.n_xg = p->N / (32 * s.nw * s.xt);
+  }
   const int64_t base = F * s.n_dt * s.n_xg;
   int split = 1;
   if (base > 0 && base < 512) {
@@ -252,8 +263,27 @@ hipError_t launch_prec(int precision, const pam::K3Args& a, int blocks, hipStrea
   }
 }
 
+template <int NSUB, int CT>
+hipError_t launch_prec16(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+  switch (precision) {
+    case PAM_PREC_SPLIT_BF16:
+      return launch_with_lds(pam::k3f16_split<__bf16, 3, NSUB, CT>, 4, pam::k3f16_split_lds<3, NSUB, CT>(), a, blocks, st);
+    case PAM_PREC_SPLIT_FP16:
+      return launch_with_lds(pam::k3f16_split<_Float16, 3, NSUB, CT>, 4, pam::k3f16_split_lds<3, NSUB, CT>(), a, blocks, st);
+    case PAM_PREC_BF16:
+      return launch_with_lds(pam::k3f16_split<__bf16, 1, NSUB, CT>, 4, pam::k3f16_split_lds<1, NSUB, CT>(), a, blocks, st);
+    case PAM_PREC_FP16:
+      return launch_with_lds(pam::k3f16_split<_Float16, 1, NSUB, CT>, 4, pam::k3f16_split_lds<1, NSUB, CT>(), a, blocks, st);
+    default:
+      return launch_with_lds(pam::k3f16_fp32<NSUB, CT>, 4, pam::k3f16_fp32_lds<NSUB, CT>(), a, blocks, st);
+  }
+}
+
 template <int NSUB>
 hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
+  if (s.ct == 4) return launch_prec16<NSUB, 4>(precision, a, blocks, st);
+  if (s.ct == 2) return launch_prec16<NSUB, 2>(precision, a, blocks, st);
+  if (s.ct == 1) return launch_prec16<NSUB, 1>(precision, a, blocks, st);
   if (s.nw == 4) return launch_prec<NSUB, 4>(precision, a, blocks, st);
   if (s.nw == 2) return launch_prec<NSUB, 2>(precision, a, blocks, st);
   return launch_prec<NSUB, 1>(precision, a, blocks, st);
@@ -378,8 +408,10 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
         const float v = basis[(size_t)s * N + x];
         const uint16_t hi = h16 ? to_fp16(v) : to_bf16(v);
         const float r = v - (h16 ? from_fp16(hi) : from_bf16(hi));
-        bhi[(size_t)x * N + s] = hi;
-        blo[(size_t)x * N + s] = h16 ? to_fp16(r) : to_bf16(r);
+        // groups of 8 slots, then x, then the 8 slots: one 16-byte piece per (group, x)
+        const size_t o = ((size_t)(s / 8) * N + x) * 8 + s % 8;
+        bhi[o] = hi;
+        blo[o] = h16 ? to_fp16(r) : to_bf16(r);
       }
   }
 
@@ -404,6 +436,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
         if (ks[b] % stride == 0) {
           ksel.push_back(ks[b] / stride);
           kz_lv.insert(kz_lv.end(), kz.begin() + (size_t)b * HQ, kz.begin() + (size_t)(b + 1) * HQ);
+          kz_lv.resize(kz_lv.size() + (pam::kz_row(N) - HQ), 0.0);
         }
       lv.n_sel = (int)ksel.size();
       if ((st = upload(p, &lv.d_ksel, ksel.data(), ksel.size())) != PAM_OK) break;
