@@ -1,0 +1,337 @@
+// K3 with fused wave roles: every wave of the workgroup both generates part of
+// the next stage's A tile and runs the matrix-core products of the current one.
+//
+// Same computation as k3_fields.hpp.  A workgroup owns one frame, 32 depths and
+// 256 columns (8 waves, one 32x32 output tile each, two waves per SIMD), so
+// every generated A element feeds 256 columns.  Only A goes through LDS: each
+// wave reads its basis operand for a stage straight from global memory (L2),
+// in a layout where a lane's operand values for the stage are contiguous, and
+// reloads the registers of a consumed k-step with the next stage's values while
+// the remaining products run.  Per stage a wave
+//   (1) runs the products of stage s (A from LDS buffer s&1, basis from
+//       registers), refilling the basis registers for stage s+1 as it goes,
+//   (2) generates its item of stage s+1's A tile into buffer (s+1)&1 from the
+//       bin's inputs staged in LDS,
+//   (3) at the first stage of a bin, writes the next bin's staged inputs (read
+//       from global memory before the products),
+//   (4) waits at the stage barrier.
+// Generation item of a thread: one slot pair (cos q, sin q) of one depth row,
+// 32 rows x 16 pairs per stage.  In the 16-bit A layout ([row][slot], 80-byte
+// rows) 32 lanes cover 8 rows x 4 adjacent pairs, so their 4-byte stores hit 32
+// distinct banks; in the FP32 layout ([slot][row]) 32 lanes cover 32 rows.
+#pragma once
+#include "k3_fields16.hpp"
+
+namespace pam {
+
+struct WgX {
+  int sp, dt, f, S, b_end;
+  StageMap sm;
+  __device__ WgX(const K3Args& a, int kc) {
+    int bid = blockIdx.x;
+    sp = bid % a.n_split; bid /= a.n_split;
+    bid /= a.n_xg;   // one column group (N = 256)
+    dt = bid % a.n_dt; bid /= a.n_dt;
+    f = bid;
+    const int b_begin = sp * a.bins_per_split;
+    b_end = min(a.n_sel, b_begin + a.bins_per_split);
+    sm = StageMap{b_begin, a.N / kc};
+    S = (b_end - b_begin) * sm.nch;
+  }
+};
+
+// Per-bin generation inputs staged in LDS (double-buffered by bin parity): the
+// folded coefficients of the frame's bin, [NSUB][N] float2 (NSUB N / 2 pieces of
+// 16 bytes), then its kz / (2 pi) row, [kz_row(N)] doubles (kz_row(N) / 2
+// pieces).  Thread p moves piece p; the kernels need NSUB N / 2 + kz_row(N) / 2
+// <= threads.
+struct BinPiece {
+  uint4 v;
+  __device__ __forceinline__ void load(const K3Args& a, int nsub, int f, int b, int tid) {
+    const int n4 = nsub * a.N / 2;
+    if (tid < n4) {
+      v = *reinterpret_cast<const uint4*>(a.coeffs + ((size_t)f * a.n_sel + b) * nsub * a.N + 2 * tid);
+    } else if (tid < n4 + kz_row(a.N) / 2) {
+      v = *reinterpret_cast<const uint4*>(a.kz + (size_t)b * kz_row(a.N) + 2 * (tid - n4));
+    }
+  }
+  // gs: [NSUB N / 2] pieces followed by the kz row
+  __device__ __forceinline__ void store(const K3Args& a, int nsub, uint4* gs, int tid) const {
+    if (tid < nsub * a.N / 2 + kz_row(a.N) / 2) gs[tid] = v;
+  }
+};
+
+// A values of one slot pair from the staged inputs of its bin:
+// vals[t][0..1] = A_t[row, 2q], A_t[row, 2q + 1] for the pair's global q.
+template <int NSUB>
+__device__ __forceinline__ void x_gen(const K3Args& a, double z, const uint4* gsb, int q,
+                                      float vals[2 * NSUB][2]) {
+  const float4* gs = reinterpret_cast<const float4*>(gsb);
+  const double* ks = reinterpret_cast<const double*>(gsb + NSUB * a.N / 2);
+  float2 h0 = make_float2(0.f, 0.f), h1 = h0;
+  if (z >= 0.0) {
+    h0 = propagator(z, ks[q], a.zero_evanescent);
+    h1 = q == 0 ? propagator(z, ks[a.N / 2], a.zero_evanescent) : h0;
+  }
+#pragma unroll
+  for (int i = 0; i < NSUB; ++i) {
+    const float4 gg = gs[i * (a.N / 2) + q];
+    const float2 a0 = cmul(h0, make_float2(gg.x, gg.y));
+    const float2 a1 = cmul(h1, make_float2(gg.z, gg.w));
+    vals[2 * i][0] = a0.x;
+    vals[2 * i][1] = a1.x;
+    vals[2 * i + 1][0] = a0.y;
+    vals[2 * i + 1][1] = a1.y;
+  }
+}
+
+__device__ __forceinline__ uint4 ld16(const void* p) { return *reinterpret_cast<const uint4*>(p); }
+
+// ---------------------------------------------------------------------------
+// FP32 operands on v_mfma_f32_32x32x2_f32.  Basis operand layout (basis_lane):
+// [N/32 chunks][N x][2 halves][16], element (slot 32 c + 2 j + h, x) at
+// ((c N + x) 2 + h) 16 + j: lane (x, h) reads its 16 values of a stage as four
+// 16-byte pieces.  LDS: A [2][2 NSUB][32 slots][32 rows] floats, then the
+// staged bin inputs [2][pieces].
+// ---------------------------------------------------------------------------
+template <int NSUB>
+__global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
+  constexpr int NT = 2 * NSUB;
+  constexpr int NP = AccCount<NSUB>::pairs;
+  constexpr int KC = 32, A_SZ = NT * KC * 32;
+  extern __shared__ float smem[];
+  float* Abuf = smem;
+  uint4* Gs = reinterpret_cast<uint4*>(smem + 2 * A_SZ);
+  const int N = a.N;
+  const int GP = NSUB * N / 2 + kz_row(N) / 2;   // staged pieces per bin
+
+  const WgX wg(a, KC);
+  const int S = wg.S, f = wg.f;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int d0 = wg.dt * 32;
+  const int r = tid & 31, ql = tid >> 5;
+  const double z = d0 + r < a.n_z ? a.z[d0 + r] : -1.0;
+  const int half = lane >> 5, col = lane & 31, xw = w * 32;
+  // this lane's basis pieces of chunk c start at ((c N + x) 2 + half) 16 floats
+  const float* bl = a.basis_lane + ((size_t)(xw + col) * 2 + half) * 16;
+
+  float accS[1][NSUB][16];
+  float accC[1][NP > 0 ? NP : 1][16];
+  v16f C[1][NT];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) accS[0][i][v] = 0.f;
+#pragma unroll
+    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[0][p][v] = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) C[0][t][v] = 0.f;
+  }
+
+  uint4 bq[4];   // basis operand of the current stage: k-steps 4g..4g+3 in bq[g]
+  BinPiece pc;
+  if (S > 0) {
+    pc.load(a, NSUB, f, wg.sm.bin(0), tid);
+    const float* b0 = bl + (size_t)wg.sm.chunk(0) * N * 32;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) bq[g] = ld16(b0 + 4 * g);
+    pc.store(a, NSUB, Gs + (wg.sm.bin(0) & 1) * GP, tid);
+    __syncthreads();
+    float vals[NT][2];
+    x_gen<NSUB>(a, z, Gs + (wg.sm.bin(0) & 1) * GP, wg.sm.chunk(0) * (KC / 2) + ql, vals);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      Abuf[(t * KC + 2 * ql) * 32 + r] = vals[t][0];
+      Abuf[(t * KC + 2 * ql + 1) * 32 + r] = vals[t][1];
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < S; ++s) {
+    const float* Ac = Abuf + (s & 1) * A_SZ;
+    const int b = wg.sm.bin(s);
+    const bool last = wg.sm.chunk(s) == wg.sm.nch - 1;
+    const bool stage_next = wg.sm.chunk(s) == 0 && b + 1 < wg.b_end;
+    const float inv = last ? a.inv_scale[(size_t)f * a.n_sel + b] : 0.f;
+    if (stage_next) pc.load(a, NSUB, f, b + 1, tid);
+    const float* bn = bl + (size_t)wg.sm.chunk(min(s + 1, S - 1)) * N * 32;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = 4 * g + jj;
+        const float bv = __uint_as_float(jj == 0 ? bq[g].x : (jj == 1 ? bq[g].y : (jj == 2 ? bq[g].z : bq[g].w)));
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float av = Ac[(t * KC + 2 * j + half) * 32 + col];
+          C[0][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, C[0][t], 0, 0, 0);
+        }
+      }
+      bq[g] = ld16(bn + 4 * g);   // next stage's k-steps 4g..4g+3
+    }
+    if (s + 1 < S) {
+      float* Ab = Abuf + ((s + 1) & 1) * A_SZ;
+      const int b1 = wg.sm.bin(s + 1);
+      float vals[NT][2];
+      x_gen<NSUB>(a, z, Gs + (b1 & 1) * GP, wg.sm.chunk(s + 1) * (KC / 2) + ql, vals);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        Ab[(t * KC + 2 * ql) * 32 + r] = vals[t][0];
+        Ab[(t * KC + 2 * ql + 1) * 32 + r] = vals[t][1];
+      }
+    }
+    if (stage_next) pc.store(a, NSUB, Gs + ((b + 1) & 1) * GP, tid);
+    if (last) {
+      fold_bin<NSUB, 1>(C, inv, accS, accC);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) C[0][t][v] = 0.f;
+    }
+    __syncthreads();
+  }
+  store_acc<NSUB, 1>(a, wg.sp, f, d0, xw, lane, accS, accC);
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit operands on v_mfma_f32_32x32x16_{bf16,f16}.  Basis operand from the
+// slot-group-major 16-bit layout ([N/8][N x][8] per plane): lane (x, h) of
+// k-step ks reads group 4 c + 2 ks + h.  LDS: A [2][2 NSUB][hi, lo][32 rows][40]
+// 16-bit, then the staged bin inputs [2][pieces].
+// ---------------------------------------------------------------------------
+template <typename T, int PASSES, int NSUB>
+__global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
+  typedef typename Mma<T>::v8 v8;
+  constexpr int NT = 2 * NSUB;
+  constexpr int NP = AccCount<NSUB>::pairs;
+  constexpr int KC = 32, RS = KC + 8;
+  constexpr int NH = PASSES == 3 ? 2 : 1;
+  constexpr int A_SZ = NT * NH * 32 * RS;
+  extern __shared__ float smem[];
+  T* Abuf = reinterpret_cast<T*>(smem);
+  uint4* Gs = reinterpret_cast<uint4*>(Abuf + 2 * A_SZ);
+  const int N = a.N;
+  const int GP = NSUB * N / 2 + kz_row(N) / 2;
+
+  const WgX wg(a, KC);
+  const int S = wg.S, f = wg.f;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int d0 = wg.dt * 32;
+  const int ql = (tid & 3) + 4 * (tid >> 7);
+  const int rr = ((tid >> 2) & 7) + 8 * ((tid >> 5) & 3);
+  const double z = d0 + rr < a.n_z ? a.z[d0 + rr] : -1.0;
+  const int half = lane >> 5, col = lane & 31, xw = w * 32;
+  const T* bhi = reinterpret_cast<const T*>(a.basis_hi) + (size_t)(xw + col) * 8;
+  const T* blo = reinterpret_cast<const T*>(a.basis_lo) + (size_t)(xw + col) * 8;
+
+  float accS[1][NSUB][16];
+  float accC[1][NP > 0 ? NP : 1][16];
+  v16f C[1][NT];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) accS[0][i][v] = 0.f;
+#pragma unroll
+    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[0][p][v] = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) C[0][t][v] = 0.f;
+  }
+
+  // basis operand of the current stage: hi and lo of k-steps 0 and 1
+  uint4 uh[2], ul[2];
+  BinPiece pc;
+  if (S > 0) {
+    pc.load(a, NSUB, f, wg.sm.bin(0), tid);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const size_t o = (size_t)(4 * wg.sm.chunk(0) + 2 * ks + half) * N * 8;
+      uh[ks] = ld16(bhi + o);
+      if (NH == 2) ul[ks] = ld16(blo + o);
+    }
+    pc.store(a, NSUB, Gs + (wg.sm.bin(0) & 1) * GP, tid);
+    __syncthreads();
+    float vals[NT][2];
+    x_gen<NSUB>(a, z, Gs + (wg.sm.bin(0) & 1) * GP, wg.sm.chunk(0) * (KC / 2) + ql, vals);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      Pair16<T> hi, lo;
+      hi.x = (T)vals[t][0];
+      hi.y = (T)vals[t][1];
+      *reinterpret_cast<Pair16<T>*>(Abuf + ((t * NH + 0) * 32 + rr) * RS + 2 * ql) = hi;
+      if (NH == 2) {
+        lo.x = (T)(vals[t][0] - (float)hi.x);
+        lo.y = (T)(vals[t][1] - (float)hi.y);
+        *reinterpret_cast<Pair16<T>*>(Abuf + ((t * NH + 1) * 32 + rr) * RS + 2 * ql) = lo;
+      }
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < S; ++s) {
+    const T* Ac = Abuf + (s & 1) * A_SZ;
+    const int b = wg.sm.bin(s);
+    const bool last = wg.sm.chunk(s) == wg.sm.nch - 1;
+    const bool stage_next = wg.sm.chunk(s) == 0 && b + 1 < wg.b_end;
+    const float inv = last ? a.inv_scale[(size_t)f * a.n_sel + b] : 0.f;
+    if (stage_next) pc.load(a, NSUB, f, b + 1, tid);
+    const int cn = wg.sm.chunk(min(s + 1, S - 1));
+#pragma unroll
+    for (int ks = 0; ks < KC / 16; ++ks) {
+      const v8 bh = __builtin_bit_cast(v8, uh[ks]);
+      v8 bl;
+      if (NH == 2) bl = __builtin_bit_cast(v8, ul[ks]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const v8 ah = *reinterpret_cast<const v8*>(Ac + ((t * NH + 0) * 32 + col) * RS + ks * 16 + 8 * half);
+        C[0][t] = Mma<T>::run(ah, bh, C[0][t]);
+        if (NH == 2) {
+          const v8 al = *reinterpret_cast<const v8*>(Ac + ((t * NH + 1) * 32 + col) * RS + ks * 16 + 8 * half);
+          C[0][t] = Mma<T>::run(ah, bl, C[0][t]);
+          C[0][t] = Mma<T>::run(al, bh, C[0][t]);
+        }
+      }
+      // next stage's operand of this k-step
+      const size_t o = (size_t)(4 * cn + 2 * ks + half) * N * 8;
+      uh[ks] = ld16(bhi + o);
+      if (NH == 2) ul[ks] = ld16(blo + o);
+    }
+    if (s + 1 < S) {
+      T* Ab = Abuf + ((s + 1) & 1) * A_SZ;
+      const int b1 = wg.sm.bin(s + 1);
+      float vals[NT][2];
+      x_gen<NSUB>(a, z, Gs + (b1 & 1) * GP, wg.sm.chunk(s + 1) * (KC / 2) + ql, vals);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        Pair16<T> hi, lo;
+        hi.x = (T)vals[t][0];
+        hi.y = (T)vals[t][1];
+        *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 0) * 32 + rr) * RS + 2 * ql) = hi;
+        if (NH == 2) {
+          lo.x = (T)(vals[t][0] - (float)hi.x);
+          lo.y = (T)(vals[t][1] - (float)hi.y);
+          *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 1) * 32 + rr) * RS + 2 * ql) = lo;
+        }
+      }
+    }
+    if (stage_next) pc.store(a, NSUB, Gs + ((b + 1) & 1) * GP, tid);
+    if (last) {
+      fold_bin<NSUB, 1>(C, inv, accS, accC);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) C[0][t][v] = 0.f;
+    }
+    __syncthreads();
+  }
+  store_acc<NSUB, 1>(a, wg.sp, f, d0, xw, lane, accS, accC);
+}
+
+// LDS bytes of the kernels above for lateral size N
+template <int NSUB>
+inline size_t k3x_fp32_lds(int N) {
+  return (size_t)2 * (2 * NSUB) * 32 * 32 * sizeof(float) + (size_t)2 * (NSUB * N / 2 + kz_row(N) / 2) * 16;
+}
+template <int PASSES, int NSUB>
+inline size_t k3x_split_lds(int N) {
+  return (size_t)2 * (2 * NSUB) * (PASSES == 3 ? 2 : 1) * 32 * 40 * 2 + (size_t)2 * (NSUB * N / 2 + kz_row(N) / 2) * 16;
+}
+
+}  // namespace pam

@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 #include "k3_fields.hpp"
 #include "k3_fields16.hpp"
+#include "k3_fields_fused.hpp"
 
 namespace {
 
@@ -96,6 +97,7 @@ struct pam_plan_s {
   float* d_masks = nullptr;    // [n_sub][L]
   int32_t col0 = 0, col_step = 1;  // grid column of element l: col0 + col_step * l
   float* d_basis = nullptr;    // [N][N] slot-major cos/sin basis (FP32 kernel)
+  float* d_basis_lane = nullptr;  // [N/32][N][2][16]: the basis in matrix-core operand order
   uint16_t* d_bhi = nullptr;   // [N/8][N][8] basis (slot groups, x, slots), 16-bit hi (split kernels)
   uint16_t* d_blo = nullptr;   // same layout, 16-bit lo
   std::vector<void*> allocs;
@@ -170,12 +172,21 @@ std::vector<int32_t> select_bins(const pam_geometry_t* g) {
 struct LaunchShape {
   int n_dt, nw, xt, n_xg, n_split, bins_per_split;
   int ct;   // > 0: 16-depth kernels with ct 16-column tiles per consumer wave
+  int fw;   // > 0: fused-role kernels with fw waves (32 depths x 32 fw columns)
 };
 
 LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
   LaunchShape s;
   s.xt = 1;
-  if (p->N % 64 == 0) {
+  s.ct = 0;
+  s.fw = 0;
+  if (p->N == 256) {
+    // 32 depths x 256 columns per workgroup, 8 waves each generating and multiplying
+    s.fw = 8;
+    s.nw = s.fw;
+    s.n_dt = (p->n_z + 31) / 32;
+    s.n_xg = p->N / (32 * s.fw);
+  } else if (p->N % 64 == 0) {
     // 16 depths x 64 ct columns per workgroup (4 consumer + 4 producer waves)
     s.ct = p->N % 256 == 0 ? 4 : (p->N % 128 == 0 ? 2 : 1);
     s.nw = 4;
@@ -183,7 +194,6 @@ LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
     s.n_xg = p->N / (64 * s.ct);
   } else {
     // 32 depths x 32 nw columns per workgroup (nw consumer + nw producer waves)
-    s.ct = 0;
     s.n_dt = (p->n_z + 31) / 32;
     const int tiles = p->N / 32;
     s.nw = (tiles % 4 == 0) ? 4 : (tiles % 2 == 0 ? 2 : 1);
@@ -279,8 +289,44 @@ hipError_t launch_prec16(int precision, const pam::K3Args& a, int blocks, hipStr
   }
 }
 
+// Fused-role kernels: the LDS size depends on N (staged bin inputs); the kernel
+// attribute is set once for the largest N they serve (256).
+template <typename K>
+hipError_t launch_fused(K kernel, int nw, size_t lds, size_t lds_max, const pam::K3Args& a, int blocks,
+                        hipStream_t st) {
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+  if (attr != hipSuccess) return attr;
+  if (lds > lds_max) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(nw * 64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int NSUB>
+hipError_t launch_precx(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+  using namespace pam;
+  const int N = a.N;
+  switch (precision) {
+    case PAM_PREC_SPLIT_BF16:
+      return launch_fused(k3x_split<__bf16, 3, NSUB>, 8, k3x_split_lds<3, NSUB>(N), k3x_split_lds<3, NSUB>(256), a,
+                          blocks, st);
+    case PAM_PREC_SPLIT_FP16:
+      return launch_fused(k3x_split<_Float16, 3, NSUB>, 8, k3x_split_lds<3, NSUB>(N), k3x_split_lds<3, NSUB>(256), a,
+                          blocks, st);
+    case PAM_PREC_BF16:
+      return launch_fused(k3x_split<__bf16, 1, NSUB>, 8, k3x_split_lds<1, NSUB>(N), k3x_split_lds<1, NSUB>(256), a,
+                          blocks, st);
+    case PAM_PREC_FP16:
+      return launch_fused(k3x_split<_Float16, 1, NSUB>, 8, k3x_split_lds<1, NSUB>(N), k3x_split_lds<1, NSUB>(256), a,
+                          blocks, st);
+    default:
+      return launch_fused(k3x_fp32<NSUB>, 8, k3x_fp32_lds<NSUB>(N), k3x_fp32_lds<NSUB>(256), a, blocks, st);
+  }
+}
+
 template <int NSUB>
 hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
+  if (s.fw == 8) return launch_precx<NSUB>(precision, a, blocks, st);
   if (s.ct == 4) return launch_prec16<NSUB, 4>(precision, a, blocks, st);
   if (s.ct == 2) return launch_prec16<NSUB, 2>(precision, a, blocks, st);
   if (s.ct == 1) return launch_prec16<NSUB, 1>(precision, a, blocks, st);
@@ -398,6 +444,14 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     }
   }
 
+  // operand order of the fused FP32 kernel: slot 32 c + 2 j + h of column x at ((c N + x) 2 + h) 16 + j
+  std::vector<float> basis_lane((size_t)N * N);
+  for (int s = 0; s < N; ++s)
+    for (int x = 0; x < N; ++x) {
+      const int c = s / 32, sl = s % 32;
+      basis_lane[(((size_t)c * N + x) * 2 + (sl & 1)) * 16 + (sl >> 1)] = basis[(size_t)s * N + x];
+    }
+
   std::vector<uint16_t> bhi, blo;
   if (is_split(p->precision)) {
     bhi.resize((size_t)N * N);
@@ -425,6 +479,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     if ((st = upload(p, &p->d_twx, twx.data(), twx.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_masks, masks.data(), masks.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_basis, basis.data(), basis.size())) != PAM_OK) break;
+    if ((st = upload(p, &p->d_basis_lane, basis_lane.data(), basis_lane.size())) != PAM_OK) break;
     // bin subsets for records of n_t / 2^j samples
     for (int stride = 1; p->n_t / stride >= kMinSamples; stride <<= 1) {
       Level lv;
@@ -540,7 +595,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   // K3: fused propagate / inverse lateral transform / cross-spectra
   {
     const LaunchShape s = k3_shape(p, F, lv->n_sel);
-    pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, accum,
+    pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, p->d_basis_lane, accum,
                   p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
     if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
