@@ -2,7 +2,8 @@
 // the next stage's A tile and runs the matrix-core products of the current one.
 //
 // Same computation as k3_fields.hpp.  A workgroup owns one frame, 32 depths and
-// 256 columns (8 waves, one 32x32 output tile each, two waves per SIMD), so
+// 256 columns (8 waves, one 32x32 output tile each, two waves per SIMD; N = 256
+// or 512, i.e. one or two column groups), so
 // every generated A element feeds 256 columns.  Only A goes through LDS: each
 // wave reads its basis operand for a stage straight from global memory (L2),
 // in a layout where a lane's operand values for the stage are contiguous, and
@@ -25,13 +26,13 @@
 namespace pam {
 
 struct WgX {
-  int sp, dt, f, S, b_end;
+  int sp, xg, dt, f, S, b_end;
   StageMap sm;
   __device__ WgX(const K3Args& a, int kc) {
     int bid = blockIdx.x;
     sp = bid % a.n_split; bid /= a.n_split;
-    bid /= a.n_xg;   // one column group (N = 256)
-    dt = bid % a.n_dt; bid /= a.n_dt;
+    xg = bid % a.n_xg;    bid /= a.n_xg;
+    dt = bid % a.n_dt;    bid /= a.n_dt;
     f = bid;
     const int b_begin = sp * a.bins_per_split;
     b_end = min(a.n_sel, b_begin + a.bins_per_split);
@@ -43,21 +44,28 @@ struct WgX {
 // Per-bin generation inputs staged in LDS (double-buffered by bin parity): the
 // folded coefficients of the frame's bin, [NSUB][N] float2 (NSUB N / 2 pieces of
 // 16 bytes), then its kz / (2 pi) row, [kz_row(N)] doubles (kz_row(N) / 2
-// pieces).  Thread p moves piece p; the kernels need NSUB N / 2 + kz_row(N) / 2
-// <= threads.
+// pieces).  Thread p moves pieces p + 512 k, k < NPC (NPC = 1 for N = 256, 2 for
+// N = 512).
+template <int NPC>
 struct BinPiece {
-  uint4 v;
-  __device__ __forceinline__ void load(const K3Args& a, int nsub, int f, int b, int tid) {
+  uint4 v[NPC];
+  __device__ __forceinline__ static uint4 piece(const K3Args& a, int nsub, int f, int b, int i) {
     const int n4 = nsub * a.N / 2;
-    if (tid < n4) {
-      v = *reinterpret_cast<const uint4*>(a.coeffs + ((size_t)f * a.n_sel + b) * nsub * a.N + 2 * tid);
-    } else if (tid < n4 + kz_row(a.N) / 2) {
-      v = *reinterpret_cast<const uint4*>(a.kz + (size_t)b * kz_row(a.N) + 2 * (tid - n4));
-    }
+    if (i < n4) return *reinterpret_cast<const uint4*>(a.coeffs + ((size_t)f * a.n_sel + b) * nsub * a.N + 2 * i);
+    return *reinterpret_cast<const uint4*>(a.kz + (size_t)b * kz_row(a.N) + 2 * (i - n4));
+  }
+  __device__ __forceinline__ void load(const K3Args& a, int nsub, int f, int b, int tid) {
+    const int np = nsub * a.N / 2 + kz_row(a.N) / 2;
+#pragma unroll
+    for (int k = 0; k < NPC; ++k)
+      if (tid + 512 * k < np) v[k] = piece(a, nsub, f, b, tid + 512 * k);
   }
   // gs: [NSUB N / 2] pieces followed by the kz row
   __device__ __forceinline__ void store(const K3Args& a, int nsub, uint4* gs, int tid) const {
-    if (tid < nsub * a.N / 2 + kz_row(a.N) / 2) gs[tid] = v;
+    const int np = nsub * a.N / 2 + kz_row(a.N) / 2;
+#pragma unroll
+    for (int k = 0; k < NPC; ++k)
+      if (tid + 512 * k < np) gs[tid + 512 * k] = v[k];
   }
 };
 
@@ -94,7 +102,7 @@ __device__ __forceinline__ uint4 ld16(const void* p) { return *reinterpret_cast<
 // 16-byte pieces.  LDS: A [2][2 NSUB][32 slots][32 rows] floats, then the
 // staged bin inputs [2][pieces].
 // ---------------------------------------------------------------------------
-template <int NSUB>
+template <int NSUB, int NPC>
 __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
   constexpr int NT = 2 * NSUB;
   constexpr int NP = AccCount<NSUB>::pairs;
@@ -113,7 +121,8 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
   const double z = d0 + r < a.n_z ? a.z[d0 + r] : -1.0;
   const int half = lane >> 5, col = lane & 31, xw = w * 32;
   // this lane's basis pieces of chunk c start at ((c N + x) 2 + half) 16 floats
-  const float* bl = a.basis_lane + ((size_t)(xw + col) * 2 + half) * 16;
+  const int xwg = wg.xg * 256;
+  const float* bl = a.basis_lane + ((size_t)(xwg + xw + col) * 2 + half) * 16;
 
   float accS[1][NSUB][16];
   float accC[1][NP > 0 ? NP : 1][16];
@@ -129,7 +138,7 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
   }
 
   uint4 bq[4];   // basis operand of the current stage: k-steps 4g..4g+3 in bq[g]
-  BinPiece pc;
+  BinPiece<NPC> pc;
   if (S > 0) {
     pc.load(a, NSUB, f, wg.sm.bin(0), tid);
     const float* b0 = bl + (size_t)wg.sm.chunk(0) * N * 32;
@@ -189,7 +198,7 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
     }
     __syncthreads();
   }
-  store_acc<NSUB, 1>(a, wg.sp, f, d0, xw, lane, accS, accC);
+  store_acc<NSUB, 1>(a, wg.sp, f, d0, xwg + xw, lane, accS, accC);
 }
 
 // ---------------------------------------------------------------------------
@@ -198,7 +207,7 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
 // k-step ks reads group 4 c + 2 ks + h.  LDS: A [2][2 NSUB][hi, lo][32 rows][40]
 // 16-bit, then the staged bin inputs [2][pieces].
 // ---------------------------------------------------------------------------
-template <typename T, int PASSES, int NSUB>
+template <typename T, int PASSES, int NSUB, int NPC>
 __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
   typedef typename Mma<T>::v8 v8;
   constexpr int NT = 2 * NSUB;
@@ -220,8 +229,9 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
   const int rr = ((tid >> 2) & 7) + 8 * ((tid >> 5) & 3);
   const double z = d0 + rr < a.n_z ? a.z[d0 + rr] : -1.0;
   const int half = lane >> 5, col = lane & 31, xw = w * 32;
-  const T* bhi = reinterpret_cast<const T*>(a.basis_hi) + (size_t)(xw + col) * 8;
-  const T* blo = reinterpret_cast<const T*>(a.basis_lo) + (size_t)(xw + col) * 8;
+  const int xwg = wg.xg * 256;
+  const T* bhi = reinterpret_cast<const T*>(a.basis_hi) + (size_t)(xwg + xw + col) * 8;
+  const T* blo = reinterpret_cast<const T*>(a.basis_lo) + (size_t)(xwg + xw + col) * 8;
 
   float accS[1][NSUB][16];
   float accC[1][NP > 0 ? NP : 1][16];
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
 
   // basis operand of the current stage: hi and lo of k-steps 0 and 1
   uint4 uh[2], ul[2];
-  BinPiece pc;
+  BinPiece<NPC> pc;
   if (S > 0) {
     pc.load(a, NSUB, f, wg.sm.bin(0), tid);
 #pragma unroll
@@ -321,7 +331,7 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
     }
     __syncthreads();
   }
-  store_acc<NSUB, 1>(a, wg.sp, f, d0, xw, lane, accS, accC);
+  store_acc<NSUB, 1>(a, wg.sp, f, d0, xwg + xw, lane, accS, accC);
 }
 
 // LDS bytes of the kernels above for lateral size N

@@ -180,12 +180,12 @@ LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
   s.xt = 1;
   s.ct = 0;
   s.fw = 0;
-  if (p->N == 256) {
+  if (p->N == 256 || p->N == 512) {
     // 32 depths x 256 columns per workgroup, 8 waves each generating and multiplying
     s.fw = 8;
     s.nw = s.fw;
     s.n_dt = (p->n_z + 31) / 32;
-    s.n_xg = p->N / (32 * s.fw);
+    s.n_xg = p->N / 256;
   } else if (p->N % 64 == 0) {
     // 16 depths x 64 ct columns per workgroup (4 consumer + 4 producer waves)
     s.ct = p->N % 256 == 0 ? 4 : (p->N % 128 == 0 ? 2 : 1);
@@ -290,7 +290,7 @@ hipError_t launch_prec16(int precision, const pam::K3Args& a, int blocks, hipStr
 }
 
 // Fused-role kernels: the LDS size depends on N (staged bin inputs); the kernel
-// attribute is set once for the largest N they serve (256).
+// attribute is set once for the largest N an instantiation serves.
 template <typename K>
 hipError_t launch_fused(K kernel, int nw, size_t lds, size_t lds_max, const pam::K3Args& a, int blocks,
                         hipStream_t st) {
@@ -302,31 +302,32 @@ hipError_t launch_fused(K kernel, int nw, size_t lds, size_t lds_max, const pam:
   return hipGetLastError();
 }
 
-template <int NSUB>
+template <int NSUB, int NPC>
 hipError_t launch_precx(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
   using namespace pam;
-  const int N = a.N;
+  const int N = a.N, NM = 256 * NPC;   // largest N served by this instantiation
   switch (precision) {
     case PAM_PREC_SPLIT_BF16:
-      return launch_fused(k3x_split<__bf16, 3, NSUB>, 8, k3x_split_lds<3, NSUB>(N), k3x_split_lds<3, NSUB>(256), a,
+      return launch_fused(k3x_split<__bf16, 3, NSUB, NPC>, 8, k3x_split_lds<3, NSUB>(N), k3x_split_lds<3, NSUB>(NM), a,
                           blocks, st);
     case PAM_PREC_SPLIT_FP16:
-      return launch_fused(k3x_split<_Float16, 3, NSUB>, 8, k3x_split_lds<3, NSUB>(N), k3x_split_lds<3, NSUB>(256), a,
-                          blocks, st);
+      return launch_fused(k3x_split<_Float16, 3, NSUB, NPC>, 8, k3x_split_lds<3, NSUB>(N),
+                          k3x_split_lds<3, NSUB>(NM), a, blocks, st);
     case PAM_PREC_BF16:
-      return launch_fused(k3x_split<__bf16, 1, NSUB>, 8, k3x_split_lds<1, NSUB>(N), k3x_split_lds<1, NSUB>(256), a,
+      return launch_fused(k3x_split<__bf16, 1, NSUB, NPC>, 8, k3x_split_lds<1, NSUB>(N), k3x_split_lds<1, NSUB>(NM), a,
                           blocks, st);
     case PAM_PREC_FP16:
-      return launch_fused(k3x_split<_Float16, 1, NSUB>, 8, k3x_split_lds<1, NSUB>(N), k3x_split_lds<1, NSUB>(256), a,
-                          blocks, st);
+      return launch_fused(k3x_split<_Float16, 1, NSUB, NPC>, 8, k3x_split_lds<1, NSUB>(N),
+                          k3x_split_lds<1, NSUB>(NM), a, blocks, st);
     default:
-      return launch_fused(k3x_fp32<NSUB>, 8, k3x_fp32_lds<NSUB>(N), k3x_fp32_lds<NSUB>(256), a, blocks, st);
+      return launch_fused(k3x_fp32<NSUB, NPC>, 8, k3x_fp32_lds<NSUB>(N), k3x_fp32_lds<NSUB>(NM), a, blocks, st);
   }
 }
 
 template <int NSUB>
 hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
-  if (s.fw == 8) return launch_precx<NSUB>(precision, a, blocks, st);
+  if (s.fw == 8) return a.N > 256 ? launch_precx<NSUB, 2>(precision, a, blocks, st)
+                                   : launch_precx<NSUB, 1>(precision, a, blocks, st);
   if (s.ct == 4) return launch_prec16<NSUB, 4>(precision, a, blocks, st);
   if (s.ct == 2) return launch_prec16<NSUB, 2>(precision, a, blocks, st);
   if (s.ct == 1) return launch_prec16<NSUB, 1>(precision, a, blocks, st);

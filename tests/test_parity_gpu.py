@@ -238,3 +238,29 @@ def test_workspace_too_small_is_rejected(pam, torch_cuda):
         assert bool((img == -7.0).all())    # nothing written
     finally:
         pam.pam_destroy(plan)
+
+
+# ------------------------------------------------------------------ lateral grid sizes
+# The fields kernel has three tilings selected by the lateral size N: 32 depths x 256
+# columns with fused wave roles (N = 256, 512), 16 depths x 64 CT columns (other
+# multiples of 64), 32 depths x 32 NW columns (the remaining multiples of 32).  Each
+# grid below reaches one of them with a ragged depth tail; the split form runs too.
+SPLIT_TOL = (1e-3, 1e-3)
+
+
+def _grid_case(n_elements, n_x, n_depths, seed):
+    g = synth.Geometry(n_elements=n_elements, pitch_m=0.3 * MM, fs_hz=20e6, c_mps=1540.0, n_samples=256,
+                       bands_hz=[(2e6, 6e6)], depths_m=(15 + 0.4 * np.arange(n_depths)) * MM, n_x=n_x,
+                       lateral="pad")
+    rng = np.random.default_rng(seed)
+    em = [synth.Emitter(-1.0 * MM, 19 * MM, "broadband"), synth.Emitter(2.0 * MM, 24 * MM, "broadband")]
+    return g, synth.render(g, em, rng, snr_db=20.0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("n_elements,n_x,n_depths", [(64, 512, 45), (32, 96, 37), (48, 192, 21)])
+def test_lateral_grid_sizes(pam, torch_cuda, precision, n_elements, n_x, n_depths):
+    g, rf = _grid_case(n_elements, n_x, n_depths, seed=n_x)
+    res = run(pam, torch_cuda, g, rf[None], precision=precision)
+    tol_i, tol_rho = (TOL_I, TOL_RHO) if precision == "fp32" else SPLIT_TOL
+    check_end_to_end(res, O.as_tax(rf, g), tol_i=tol_i, tol_rho=tol_rho)
