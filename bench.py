@@ -89,7 +89,7 @@ def source_digest() -> str:
     """SHA-256 of the fields kernel's sources: traffic counters stay valid only for this code."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("k3_fields.hpp", "kernels.hpp"):
+    for name in ("kernels.hpp", "k3_fields.hpp", "k3_fields16.hpp", "k3_fields_fused.hpp"):
         with open(os.path.join(ROOT, "paper_2412_02413_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

@@ -137,6 +137,20 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
     for (int t = 0; t < NT; ++t) C[0][t][v] = 0.f;
   }
 
+  // generation of stage s (into buffer s&1), after the products of the previous
+  // stage (the 16-bit kernel staggers it between the two waves of a SIMD; with the
+  // longer FP32 products that measured slower here)
+  const bool gen_first = false;
+  auto gen_next = [&](int s) {
+    float* Ab = Abuf + (s & 1) * A_SZ;
+    float vals[NT][2];
+    x_gen<NSUB>(a, z, Gs + (wg.sm.bin(s) & 1) * GP, wg.sm.chunk(s) * (KC / 2) + ql, vals);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      Ab[(t * KC + 2 * ql) * 32 + r] = vals[t][0];
+      Ab[(t * KC + 2 * ql + 1) * 32 + r] = vals[t][1];
+    }
+  };
   uint4 bq[4];   // basis operand of the current stage: k-steps 4g..4g+3 in bq[g]
   BinPiece<NPC> pc;
   if (S > 0) {
@@ -162,6 +176,7 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
     const bool stage_next = wg.sm.chunk(s) == 0 && b + 1 < wg.b_end;
     const float inv = last ? a.inv_scale[(size_t)f * a.n_sel + b] : 0.f;
     if (stage_next) pc.load(a, NSUB, f, b + 1, tid);
+    if (gen_first && s + 1 < S) gen_next(s + 1);
     const float* bn = bl + (size_t)wg.sm.chunk(min(s + 1, S - 1)) * N * 32;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -177,17 +192,7 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
       }
       bq[g] = ld16(bn + 4 * g);   // next stage's k-steps 4g..4g+3
     }
-    if (s + 1 < S) {
-      float* Ab = Abuf + ((s + 1) & 1) * A_SZ;
-      const int b1 = wg.sm.bin(s + 1);
-      float vals[NT][2];
-      x_gen<NSUB>(a, z, Gs + (b1 & 1) * GP, wg.sm.chunk(s + 1) * (KC / 2) + ql, vals);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        Ab[(t * KC + 2 * ql) * 32 + r] = vals[t][0];
-        Ab[(t * KC + 2 * ql + 1) * 32 + r] = vals[t][1];
-      }
-    }
+    if (!gen_first && s + 1 < S) gen_next(s + 1);
     if (stage_next) pc.store(a, NSUB, Gs + ((b + 1) & 1) * GP, tid);
     if (last) {
       fold_bin<NSUB, 1>(C, inv, accS, accC);
@@ -246,6 +251,27 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
     for (int t = 0; t < NT; ++t) C[0][t][v] = 0.f;
   }
 
+  // generation of stage s (into buffer s&1).  The two waves of a SIMD (w and w + 4)
+  // order their work differently within a stage, one generating before its products
+  // and one after, so one wave's VALU work meets the other's matrix-core products.
+  const bool gen_first = w >= 4;
+  auto gen_next = [&](int s) {
+    T* Ab = Abuf + (s & 1) * A_SZ;
+    float vals[NT][2];
+    x_gen<NSUB>(a, z, Gs + (wg.sm.bin(s) & 1) * GP, wg.sm.chunk(s) * (KC / 2) + ql, vals);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      Pair16<T> hi, lo;
+      hi.x = (T)vals[t][0];
+      hi.y = (T)vals[t][1];
+      *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 0) * 32 + rr) * RS + 2 * ql) = hi;
+      if (NH == 2) {
+        lo.x = (T)(vals[t][0] - (float)hi.x);
+        lo.y = (T)(vals[t][1] - (float)hi.y);
+        *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 1) * 32 + rr) * RS + 2 * ql) = lo;
+      }
+    }
+  };
   // basis operand of the current stage: hi and lo of k-steps 0 and 1
   uint4 uh[2], ul[2];
   BinPiece<NPC> pc;
@@ -282,6 +308,7 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
     const bool stage_next = wg.sm.chunk(s) == 0 && b + 1 < wg.b_end;
     const float inv = last ? a.inv_scale[(size_t)f * a.n_sel + b] : 0.f;
     if (stage_next) pc.load(a, NSUB, f, b + 1, tid);
+    if (gen_first && s + 1 < S) gen_next(s + 1);
     const int cn = wg.sm.chunk(min(s + 1, S - 1));
 #pragma unroll
     for (int ks = 0; ks < KC / 16; ++ks) {
@@ -303,24 +330,7 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
       uh[ks] = ld16(bhi + o);
       if (NH == 2) ul[ks] = ld16(blo + o);
     }
-    if (s + 1 < S) {
-      T* Ab = Abuf + ((s + 1) & 1) * A_SZ;
-      const int b1 = wg.sm.bin(s + 1);
-      float vals[NT][2];
-      x_gen<NSUB>(a, z, Gs + (b1 & 1) * GP, wg.sm.chunk(s + 1) * (KC / 2) + ql, vals);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        Pair16<T> hi, lo;
-        hi.x = (T)vals[t][0];
-        hi.y = (T)vals[t][1];
-        *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 0) * 32 + rr) * RS + 2 * ql) = hi;
-        if (NH == 2) {
-          lo.x = (T)(vals[t][0] - (float)hi.x);
-          lo.y = (T)(vals[t][1] - (float)hi.y);
-          *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 1) * 32 + rr) * RS + 2 * ql) = lo;
-        }
-      }
-    }
+    if (!gen_first && s + 1 < S) gen_next(s + 1);
     if (stage_next) pc.store(a, NSUB, Gs + ((b + 1) & 1) * GP, tid);
     if (last) {
       fold_bin<NSUB, 1>(C, inv, accS, accC);
