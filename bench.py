@@ -175,14 +175,47 @@ def surrogate_entry(geom, rf, plain_images, fps_plain, precision, steps, warmup,
             "weights": os.path.relpath(path, ROOT)}
 
 
+def pcie_inclusive(geom, rf_host, precision, steps, dev):
+    """Throughput with the RF copied host->device (pinned) and the images copied back in
+    every launch, all on one stream: the rate a caller holding frames in host memory sees."""
+    import torch
+    from paper_2412_02413_amd import pam
+    F = rf_host.shape[0]
+    plan = pam.pam_plan(geom, 0, precision)
+    try:
+        rf_pin = torch.from_numpy(rf_host).pin_memory()
+        img_pin = torch.empty((F, geom.n_z, geom.n_x), dtype=torch.float32).pin_memory()
+        rf_dev = torch.empty(rf_pin.shape, dtype=torch.float32, device=dev)
+        image = torch.empty((F, geom.n_z, geom.n_x), device=dev)
+        ws = pam.alloc_workspace(plan, F, geom.n_samples, dev)
+        stream = torch.cuda.current_stream(dev)
+
+        def one():
+            rf_dev.copy_(rf_pin, non_blocking=True)
+            pam.pam_as_tax(plan, rf_dev, image, None, None, ws, stream)
+            img_pin.copy_(image, non_blocking=True)
+
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        pam.pam_destroy(plan)
+    return {"frames_per_s": round(F * steps / wall, 2), "ms_per_step": round(1e3 * wall / steps, 3),
+            "steps": steps, "copies": "RF host->device and image device->host per launch, pinned host memory"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64, help="frames per launch")
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--latency-calls", type=int, default=200)
+    ap.add_argument("--latency-calls", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="split_bf16,split_fp16,bf16,fp16",
                     help="other precision forms measured beside the main one (comma list, '' for none)")
@@ -303,6 +336,8 @@ def main():
             log(f"surrogate: {sur}")
         else:
             log(f"surrogate weights not found at {args.surrogate}: no surrogate entry")
+    pcie = pcie_inclusive(geom, rf_host, args.precision, max(3, args.steps // 4), dev)
+    log(f"with host copies: {pcie}")
     if args.copy_calibration:
         copy_calibration(dev)
 
@@ -337,6 +372,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "surrogate": sur,
+        "pcie_inclusive": pcie,
     }
     rec.update(out)
     ev.close()
