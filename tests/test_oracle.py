@@ -54,6 +54,24 @@ def test_bins_reproduce_wideband_count():
         assert ks[0] == 173 and ks[-1] == 862
 
 
+def test_band_union_is_the_union_of_its_bands():
+    """Eq. 3's Omega as a union of closed windows (frequency-selective maps): the bin set
+    is the disjoint union of each window's bins, and every sum over Omega (S_i, C_ij, E)
+    is the sum of the per-window sums."""
+    g = small_cfg1(n_depths=9)
+    bands = [(1.2e6, 1.8e6), (2.8e6, 3.4e6)]
+    k_union = O.bins(g.fs_hz, g.n_samples, bands)
+    k_parts = [O.bins(g.fs_hz, g.n_samples, [b]) for b in bands]
+    assert len(set(k_parts[0]) & set(k_parts[1])) == 0
+    np.testing.assert_array_equal(k_union, np.sort(np.concatenate(k_parts)))
+    rf = synth.cfg1_frame(3)
+    ru = O.as_tax(rf, g.replace(bands_hz=bands))
+    r1 = O.as_tax(rf, g.replace(bands_hz=[bands[0]]))
+    r2 = O.as_tax(rf, g.replace(bands_hz=[bands[1]]))
+    for key in ("E", "S", "C"):
+        np.testing.assert_allclose(ru[key], r1[key] + r2[key], rtol=1e-12, atol=1e-12 * np.abs(ru[key]).max())
+
+
 def test_propagator_table_sizes_match_printed_memory():
     # complex64 n_w x n_z x n_x tables: the printed MB figures are MiB of 8-byte entries
     for row in _golden("counts.txt"):

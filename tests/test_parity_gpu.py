@@ -264,3 +264,12 @@ def test_lateral_grid_sizes(pam, torch_cuda, precision, n_elements, n_x, n_depth
     res = run(pam, torch_cuda, g, rf[None], precision=precision)
     tol_i, tol_rho = (TOL_I, TOL_RHO) if precision == "fp32" else SPLIT_TOL
     check_end_to_end(res, O.as_tax(rf, g), tol_i=tol_i, tol_rho=tol_rho)
+
+
+def test_band_union(pam, torch_cuda, cfg1_batch):
+    """Omega as a union of two disjoint windows (frequency-selective map)."""
+    g = synth.cfg1_geometry().replace(bands_hz=[(1.2e6, 1.8e6), (2.8e6, 3.4e6)],
+                                      depths_m=(20 + 0.5 * np.arange(45)) * MM)
+    res = run(pam, torch_cuda, g, cfg1_batch[:1])
+    assert len(res["bins"]) == len(O.bins(g.fs_hz, g.n_samples, g.bands_hz))
+    check_end_to_end(res, O.as_tax(cfg1_batch[0], g))
