@@ -175,6 +175,73 @@ def surrogate_entry(geom, rf, plain_images, fps_plain, precision, steps, warmup,
             "weights": os.path.relpath(path, ROOT)}
 
 
+def stage_rooflines(geom, n_sel: int, F: int, lay, stage_ms: dict) -> dict:
+    """The smaller kernels against their own bounds, from the live stage times:
+    K1 (time FFT) and K4 (NCC / weight / image) against HBM bandwidth by the bytes they
+    must move, K2 (apodized lateral DFT) against the FP32 vector rate (non-packed FMA,
+    78.6 TFLOP/s) by its direct-DFT flops."""
+    pix = geom.n_z * geom.n_x
+    plane = F * pix * 4
+    k1_bytes = F * geom.n_elements * geom.n_samples * 4 + F * n_sel * geom.n_elements * 8
+    # accumulators in, energy + weight out; weight + energy in, image + NNCC out
+    k4_bytes = lay.n_split * lay.n_acc * plane + 2 * plane + 2 * plane + 2 * plane
+    k2_flops = F * n_sel * geom.n_sub * geom.n_x * geom.n_elements * 8.0
+    out = {}
+    for name, key, amount, peak, unit, scale in (
+            ("time_fft", "time_fft", k1_bytes, HBM_PEAK_GBS, "GB/s", 1e9),
+            ("finalize", "finalize", k4_bytes, HBM_PEAK_GBS, "GB/s", 1e9),
+            ("lateral", "lateral", k2_flops, 78.6, "TFLOP/s", 1e12)):
+        ms = stage_ms[key]
+        ach = amount / (ms * 1e-3) / scale
+        out[name] = {"bound": "hbm" if unit == "GB/s" else "valu", "achieved": round(ach, 2), "peak": peak,
+                     "unit": unit, "frac": round(ach / peak, 4), "per_launch": amount, "ms": round(ms, 4)}
+    return out
+
+
+def paper_shape(precisions, steps: int, dev) -> dict:
+    """The paper's image shape (128 elements, 2048 samples at 35.6 MHz, 2x zero-stuffing to 256
+    columns, 300 depths; 690 and 128 bins): ms per frame in 64-frame launches and single-frame
+    latency, to quote beside the paper's own per-image times (other hardware: context only)."""
+    import torch
+    from paper_2412_02413_amd import pam, synth
+    out = {}
+    for n_bins in (690, 128):
+        g = synth.paper_geometry(n_bins)
+        frames = np.stack([synth.paper_frame(s, n_bins) for s in range(8)])
+        rf = torch.from_numpy(np.concatenate([frames] * 8)).to(dev)
+        F = rf.shape[0]
+        for prec in precisions:
+            plan = pam.pam_plan(g, 0, prec)
+            try:
+                image = torch.empty((F, g.n_z, g.n_x), device=dev)
+                ws = pam.alloc_workspace(plan, F, g.n_samples, dev)
+                stream = torch.cuda.current_stream(dev)
+                pam.pam_as_tax(plan, rf, image, None, None, ws, stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    pam.pam_as_tax(plan, rf, image, None, None, ws, stream)
+                torch.cuda.synchronize()
+                ms_frame = 1e3 * (time.perf_counter() - t0) / (steps * F)
+                img1 = torch.empty((1, g.n_z, g.n_x), device=dev)
+                ws1 = pam.alloc_workspace(plan, 1, g.n_samples, dev)
+                lat = []
+                for c in range(23):
+                    torch.cuda.synchronize()
+                    tw = time.perf_counter()
+                    pam.pam_as_tax(plan, rf[c % F: c % F + 1], img1, None, None, ws1, stream)
+                    torch.cuda.synchronize()
+                    if c >= 3:
+                        lat.append(1e3 * (time.perf_counter() - tw))
+                out[f"{n_bins}_bins_{prec}"] = {"ms_per_frame_batched": round(ms_frame, 4),
+                                                "ms_single_frame_p50_wall": round(float(np.median(lat)), 4),
+                                                "bins": plan.info.n_bins}
+            finally:
+                pam.pam_destroy(plan)
+    out["paper_context"] = "RTX 4090, CUDA: 9.8 ms (690 bins) and 1.8 ms (128 bins) per image (Table III)"
+    return out
+
+
 def pcie_inclusive(geom, rf_host, precision, steps, dev):
     """Throughput with the RF copied host->device (pinned) and the images copied back in
     every launch, all on one stream: the rate a caller holding frames in host memory sees."""
@@ -222,6 +289,8 @@ def main():
     ap.add_argument("--surrogate", default=os.path.join(ROOT, "paper_2412_02413_amd", "weights",
                                                         "surrogate_l4_b32.safetensors"),
                     help="surrogate weights measured beside plain AS-TAX ('' for none)")
+    ap.add_argument("--no-paper-shape", dest="paper_shape", action="store_false",
+                    help="skip the paper-shape (690 / 128 bins, 300 x 256) context timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with plain device copies of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -338,6 +407,10 @@ def main():
             log(f"surrogate weights not found at {args.surrogate}: no surrogate entry")
     pcie = pcie_inclusive(geom, rf_host, args.precision, max(3, args.steps // 4), dev)
     log(f"with host copies: {pcie}")
+    stages_roof = stage_rooflines(geom, n_sel, F, main_res["layout"], stage_ms)
+    pshape = paper_shape([args.precision, "split_bf16"], 5, dev) if args.paper_shape else None
+    if pshape:
+        log(f"paper shape: {pshape}")
     if args.copy_calibration:
         copy_calibration(dev)
 
@@ -362,6 +435,7 @@ def main():
                                   "p99_host_wall": round(float(np.percentile(lat_wall, 99)), 4),
                                   "calls": len(lat_gpu), "frames_per_call": 1} if lat_gpu else None),
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
+        "stage_rooflines": stages_roof,
         "roofline": {"kernel": "fields (propagate + DFT-GEMM + cross-spectra)", "bound": "mfma",
                      "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
@@ -373,6 +447,7 @@ def main():
         "variants": variants,
         "surrogate": sur,
         "pcie_inclusive": pcie,
+        "paper_shape": pshape,
     }
     rec.update(out)
     ev.close()
