@@ -96,17 +96,22 @@ __device__ __forceinline__ void x_gen(const K3Args& a, double z, const uint4* gs
 __device__ __forceinline__ uint4 ld16(const void* p) { return *reinterpret_cast<const uint4*>(p); }
 
 // ---------------------------------------------------------------------------
-// FP32 operands on v_mfma_f32_32x32x2_f32.  Basis operand layout (basis_lane):
-// [N/32 chunks][N x][2 halves][16], element (slot 32 c + 2 j + h, x) at
-// ((c N + x) 2 + h) 16 + j: lane (x, h) reads its 16 values of a stage as four
-// 16-byte pieces.  LDS: A [2][2 NSUB][32 slots][32 rows] floats, then the
-// staged bin inputs [2][pieces].
+// FP32 operands on v_mfma_f32_32x32x2_f32, KC slots per stage (32 or 64).
+// Basis operand layout (basis_lane): [N/32 chunks][N x][2 halves][16], element
+// (slot 32 c + 2 j + h, x) at ((c N + x) 2 + h) 16 + j, so lane (x, h) reads the
+// values of 4 consecutive k-steps (8 slots) as one 16-byte piece.  The pieces of
+// the current and next stage flow through a window of 4 registers: after the
+// products of piece g, piece g + 4 (of this stage or the next) is loaded into its
+// register.  LDS: A [2][2 NSUB][KC slots][32 rows] floats, then the staged bin
+// inputs [2][pieces].  Items of thread p: row p & 31, slot pairs (p >> 5) + 16 k.
 // ---------------------------------------------------------------------------
-template <int NSUB, int NPC>
+template <int NSUB, int NPC, int KC>
 __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
   constexpr int NT = 2 * NSUB;
   constexpr int NP = AccCount<NSUB>::pairs;
-  constexpr int KC = 32, A_SZ = NT * KC * 32;
+  constexpr int A_SZ = NT * KC * 32;
+  constexpr int NG = KC / 8;     // 16-byte basis pieces per lane per stage
+  constexpr int GI = KC / 32;    // generation items per thread per stage
   extern __shared__ float smem[];
   float* Abuf = smem;
   uint4* Gs = reinterpret_cast<uint4*>(smem + 2 * A_SZ);
@@ -117,12 +122,16 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
   const int S = wg.S, f = wg.f;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int d0 = wg.dt * 32;
-  const int r = tid & 31, ql = tid >> 5;
+  const int r = tid & 31;
   const double z = d0 + r < a.n_z ? a.z[d0 + r] : -1.0;
   const int half = lane >> 5, col = lane & 31, xw = w * 32;
-  // this lane's basis pieces of chunk c start at ((c N + x) 2 + half) 16 floats
   const int xwg = wg.xg * 256;
   const float* bl = a.basis_lane + ((size_t)(xwg + xw + col) * 2 + half) * 16;
+  // piece g (0 <= g < NG) of stage s: global 8-slot group G = NG chunk(s) + g
+  auto piece = [&](int s, int g) {
+    const int G = NG * wg.sm.chunk(s) + g;
+    return ld16(bl + (size_t)(G >> 2) * N * 32 + 4 * (G & 3));
+  };
 
   float accS[1][NSUB][16];
   float accC[1][NP > 0 ? NP : 1][16];
@@ -137,36 +146,30 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
     for (int t = 0; t < NT; ++t) C[0][t][v] = 0.f;
   }
 
-  // generation of stage s (into buffer s&1), after the products of the previous
-  // stage (the 16-bit kernel staggers it between the two waves of a SIMD; with the
-  // longer FP32 products that measured slower here)
-  const bool gen_first = false;
-  auto gen_next = [&](int s) {
+  // generation of stage s into buffer s&1 (after the products of the previous stage)
+  auto gen = [&](int s) {
     float* Ab = Abuf + (s & 1) * A_SZ;
-    float vals[NT][2];
-    x_gen<NSUB>(a, z, Gs + (wg.sm.bin(s) & 1) * GP, wg.sm.chunk(s) * (KC / 2) + ql, vals);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      Ab[(t * KC + 2 * ql) * 32 + r] = vals[t][0];
-      Ab[(t * KC + 2 * ql + 1) * 32 + r] = vals[t][1];
+    for (int k = 0; k < GI; ++k) {
+      const int ql = (tid >> 5) + 16 * k;
+      float vals[NT][2];
+      x_gen<NSUB>(a, z, Gs + (wg.sm.bin(s) & 1) * GP, wg.sm.chunk(s) * (KC / 2) + ql, vals);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        Ab[(t * KC + 2 * ql) * 32 + r] = vals[t][0];
+        Ab[(t * KC + 2 * ql + 1) * 32 + r] = vals[t][1];
+      }
     }
   };
-  uint4 bq[4];   // basis operand of the current stage: k-steps 4g..4g+3 in bq[g]
+  uint4 bq[4];   // window of basis pieces: piece g lives in bq[g & 3]
   BinPiece<NPC> pc;
   if (S > 0) {
     pc.load(a, NSUB, f, wg.sm.bin(0), tid);
-    const float* b0 = bl + (size_t)wg.sm.chunk(0) * N * 32;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) bq[g] = ld16(b0 + 4 * g);
+    for (int g = 0; g < 4; ++g) bq[g] = g < NG ? piece(0, g) : piece(min(1, S - 1), g - NG);
     pc.store(a, NSUB, Gs + (wg.sm.bin(0) & 1) * GP, tid);
     __syncthreads();
-    float vals[NT][2];
-    x_gen<NSUB>(a, z, Gs + (wg.sm.bin(0) & 1) * GP, wg.sm.chunk(0) * (KC / 2) + ql, vals);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      Abuf[(t * KC + 2 * ql) * 32 + r] = vals[t][0];
-      Abuf[(t * KC + 2 * ql + 1) * 32 + r] = vals[t][1];
-    }
+    gen(0);
   }
   __syncthreads();
   for (int s = 0; s < S; ++s) {
@@ -176,23 +179,23 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
     const bool stage_next = wg.sm.chunk(s) == 0 && b + 1 < wg.b_end;
     const float inv = last ? a.inv_scale[(size_t)f * a.n_sel + b] : 0.f;
     if (stage_next) pc.load(a, NSUB, f, b + 1, tid);
-    if (gen_first && s + 1 < S) gen_next(s + 1);
-    const float* bn = bl + (size_t)wg.sm.chunk(min(s + 1, S - 1)) * N * 32;
+    const int sn = min(s + 1, S - 1);
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < NG; ++g) {
+      const uint4 pg = bq[g & 3];
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
         const int j = 4 * g + jj;
-        const float bv = __uint_as_float(jj == 0 ? bq[g].x : (jj == 1 ? bq[g].y : (jj == 2 ? bq[g].z : bq[g].w)));
+        const float bv = __uint_as_float(jj == 0 ? pg.x : (jj == 1 ? pg.y : (jj == 2 ? pg.z : pg.w)));
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const float av = Ac[(t * KC + 2 * j + half) * 32 + col];
           C[0][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, C[0][t], 0, 0, 0);
         }
       }
-      bq[g] = ld16(bn + 4 * g);   // next stage's k-steps 4g..4g+3
+      bq[g & 3] = g + 4 < NG ? piece(s, g + 4) : piece(sn, g + 4 - NG);
     }
-    if (!gen_first && s + 1 < S) gen_next(s + 1);
+    if (s + 1 < S) gen(s + 1);
     if (stage_next) pc.store(a, NSUB, Gs + ((b + 1) & 1) * GP, tid);
     if (last) {
       fold_bin<NSUB, 1>(C, inv, accS, accC);
@@ -207,19 +210,24 @@ __global__ __launch_bounds__(512, 1) void k3x_fp32(K3Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// 16-bit operands on v_mfma_f32_32x32x16_{bf16,f16}.  Basis operand from the
-// slot-group-major 16-bit layout ([N/8][N x][8] per plane): lane (x, h) of
-// k-step ks reads group 4 c + 2 ks + h.  LDS: A [2][2 NSUB][hi, lo][32 rows][40]
-// 16-bit, then the staged bin inputs [2][pieces].
+// 16-bit operands on v_mfma_f32_32x32x16_{bf16,f16}, KC slots per stage (32 or 64,
+// KC / 16 k-steps).  Basis operand from the slot-group-major 16-bit layout
+// ([N/8][N x][8] per plane): lane (x, h) of k-step ks reads group
+// (KC / 8) chunk + 2 ks + h; the hi and lo pieces flow through a window of two
+// k-steps.  LDS: A [2][2 NSUB][hi, lo][32 rows][KC + 8] 16-bit, then the staged
+// bin inputs.  Items of thread p: slot pairs (p & 3) + 4 ((p >> 7) & 3) + 16 k,
+// row ((p >> 2) & 7) + 8 ((p >> 5) & 3).
 // ---------------------------------------------------------------------------
-template <typename T, int PASSES, int NSUB, int NPC>
+template <typename T, int PASSES, int NSUB, int NPC, int KC>
 __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
   typedef typename Mma<T>::v8 v8;
   constexpr int NT = 2 * NSUB;
   constexpr int NP = AccCount<NSUB>::pairs;
-  constexpr int KC = 32, RS = KC + 8;
+  constexpr int RS = KC + 8;
   constexpr int NH = PASSES == 3 ? 2 : 1;
   constexpr int A_SZ = NT * NH * 32 * RS;
+  constexpr int NKS = KC / 16;
+  constexpr int GI = KC / 32;
   extern __shared__ float smem[];
   T* Abuf = reinterpret_cast<T*>(smem);
   uint4* Gs = reinterpret_cast<uint4*>(Abuf + 2 * A_SZ);
@@ -230,13 +238,14 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
   const int S = wg.S, f = wg.f;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int d0 = wg.dt * 32;
-  const int ql = (tid & 3) + 4 * (tid >> 7);
+  const int qb = (tid & 3) + 4 * ((tid >> 7) & 3);
   const int rr = ((tid >> 2) & 7) + 8 * ((tid >> 5) & 3);
   const double z = d0 + rr < a.n_z ? a.z[d0 + rr] : -1.0;
   const int half = lane >> 5, col = lane & 31, xw = w * 32;
   const int xwg = wg.xg * 256;
   const T* bhi = reinterpret_cast<const T*>(a.basis_hi) + (size_t)(xwg + xw + col) * 8;
   const T* blo = reinterpret_cast<const T*>(a.basis_lo) + (size_t)(xwg + xw + col) * 8;
+  auto goff = [&](int s, int ks) { return (size_t)((KC / 8) * wg.sm.chunk(s) + 2 * ks + half) * N * 8; };
 
   float accS[1][NSUB][16];
   float accC[1][NP > 0 ? NP : 1][16];
@@ -251,54 +260,45 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
     for (int t = 0; t < NT; ++t) C[0][t][v] = 0.f;
   }
 
-  // generation of stage s (into buffer s&1).  The two waves of a SIMD (w and w + 4)
+  // generation of stage s into buffer s&1.  The two waves of a SIMD (w and w + 4)
   // order their work differently within a stage, one generating before its products
   // and one after, so one wave's VALU work meets the other's matrix-core products.
   const bool gen_first = w >= 4;
-  auto gen_next = [&](int s) {
+  auto gen = [&](int s) {
     T* Ab = Abuf + (s & 1) * A_SZ;
-    float vals[NT][2];
-    x_gen<NSUB>(a, z, Gs + (wg.sm.bin(s) & 1) * GP, wg.sm.chunk(s) * (KC / 2) + ql, vals);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      Pair16<T> hi, lo;
-      hi.x = (T)vals[t][0];
-      hi.y = (T)vals[t][1];
-      *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 0) * 32 + rr) * RS + 2 * ql) = hi;
-      if (NH == 2) {
-        lo.x = (T)(vals[t][0] - (float)hi.x);
-        lo.y = (T)(vals[t][1] - (float)hi.y);
-        *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 1) * 32 + rr) * RS + 2 * ql) = lo;
+    for (int k = 0; k < GI; ++k) {
+      const int ql = qb + 16 * k;
+      float vals[NT][2];
+      x_gen<NSUB>(a, z, Gs + (wg.sm.bin(s) & 1) * GP, wg.sm.chunk(s) * (KC / 2) + ql, vals);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        Pair16<T> hi, lo;
+        hi.x = (T)vals[t][0];
+        hi.y = (T)vals[t][1];
+        *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 0) * 32 + rr) * RS + 2 * ql) = hi;
+        if (NH == 2) {
+          lo.x = (T)(vals[t][0] - (float)hi.x);
+          lo.y = (T)(vals[t][1] - (float)hi.y);
+          *reinterpret_cast<Pair16<T>*>(Ab + ((t * NH + 1) * 32 + rr) * RS + 2 * ql) = lo;
+        }
       }
     }
   };
-  // basis operand of the current stage: hi and lo of k-steps 0 and 1
+  // window of basis operands: k-step ks lives in uh/ul[ks & 1]
   uint4 uh[2], ul[2];
   BinPiece<NPC> pc;
   if (S > 0) {
     pc.load(a, NSUB, f, wg.sm.bin(0), tid);
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const size_t o = (size_t)(4 * wg.sm.chunk(0) + 2 * ks + half) * N * 8;
+      const size_t o = ks < NKS ? goff(0, ks) : goff(min(1, S - 1), ks - NKS);
       uh[ks] = ld16(bhi + o);
       if (NH == 2) ul[ks] = ld16(blo + o);
     }
     pc.store(a, NSUB, Gs + (wg.sm.bin(0) & 1) * GP, tid);
     __syncthreads();
-    float vals[NT][2];
-    x_gen<NSUB>(a, z, Gs + (wg.sm.bin(0) & 1) * GP, wg.sm.chunk(0) * (KC / 2) + ql, vals);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      Pair16<T> hi, lo;
-      hi.x = (T)vals[t][0];
-      hi.y = (T)vals[t][1];
-      *reinterpret_cast<Pair16<T>*>(Abuf + ((t * NH + 0) * 32 + rr) * RS + 2 * ql) = hi;
-      if (NH == 2) {
-        lo.x = (T)(vals[t][0] - (float)hi.x);
-        lo.y = (T)(vals[t][1] - (float)hi.y);
-        *reinterpret_cast<Pair16<T>*>(Abuf + ((t * NH + 1) * 32 + rr) * RS + 2 * ql) = lo;
-      }
-    }
+    gen(0);
   }
   __syncthreads();
   for (int s = 0; s < S; ++s) {
@@ -308,13 +308,13 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
     const bool stage_next = wg.sm.chunk(s) == 0 && b + 1 < wg.b_end;
     const float inv = last ? a.inv_scale[(size_t)f * a.n_sel + b] : 0.f;
     if (stage_next) pc.load(a, NSUB, f, b + 1, tid);
-    if (gen_first && s + 1 < S) gen_next(s + 1);
-    const int cn = wg.sm.chunk(min(s + 1, S - 1));
+    if (gen_first && s + 1 < S) gen(s + 1);
+    const int sn = min(s + 1, S - 1);
 #pragma unroll
-    for (int ks = 0; ks < KC / 16; ++ks) {
-      const v8 bh = __builtin_bit_cast(v8, uh[ks]);
+    for (int ks = 0; ks < NKS; ++ks) {
+      const v8 bh = __builtin_bit_cast(v8, uh[ks & 1]);
       v8 bl;
-      if (NH == 2) bl = __builtin_bit_cast(v8, ul[ks]);
+      if (NH == 2) bl = __builtin_bit_cast(v8, ul[ks & 1]);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const v8 ah = *reinterpret_cast<const v8*>(Ac + ((t * NH + 0) * 32 + col) * RS + ks * 16 + 8 * half);
@@ -325,12 +325,12 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
           C[0][t] = Mma<T>::run(al, bh, C[0][t]);
         }
       }
-      // next stage's operand of this k-step
-      const size_t o = (size_t)(4 * cn + 2 * ks + half) * N * 8;
-      uh[ks] = ld16(bhi + o);
-      if (NH == 2) ul[ks] = ld16(blo + o);
+      // k-step ks + 2 of this stage or the next
+      const size_t o = ks + 2 < NKS ? goff(s, ks + 2) : goff(sn, ks + 2 - NKS);
+      uh[ks & 1] = ld16(bhi + o);
+      if (NH == 2) ul[ks & 1] = ld16(blo + o);
     }
-    if (!gen_first && s + 1 < S) gen_next(s + 1);
+    if (!gen_first && s + 1 < S) gen(s + 1);
     if (stage_next) pc.store(a, NSUB, Gs + ((b + 1) & 1) * GP, tid);
     if (last) {
       fold_bin<NSUB, 1>(C, inv, accS, accC);
@@ -345,13 +345,14 @@ __global__ __launch_bounds__(512, 1) void k3x_split(K3Args a) {
 }
 
 // LDS bytes of the kernels above for lateral size N
-template <int NSUB>
+template <int NSUB, int KC>
 inline size_t k3x_fp32_lds(int N) {
-  return (size_t)2 * (2 * NSUB) * 32 * 32 * sizeof(float) + (size_t)2 * (NSUB * N / 2 + kz_row(N) / 2) * 16;
+  return (size_t)2 * (2 * NSUB) * KC * 32 * sizeof(float) + (size_t)2 * (NSUB * N / 2 + kz_row(N) / 2) * 16;
 }
-template <int PASSES, int NSUB>
+template <int PASSES, int NSUB, int KC>
 inline size_t k3x_split_lds(int N) {
-  return (size_t)2 * (2 * NSUB) * (PASSES == 3 ? 2 : 1) * 32 * 40 * 2 + (size_t)2 * (NSUB * N / 2 + kz_row(N) / 2) * 16;
+  return (size_t)2 * (2 * NSUB) * (PASSES == 3 ? 2 : 1) * 32 * (KC + 8) * 2 +
+         (size_t)2 * (NSUB * N / 2 + kz_row(N) / 2) * 16;
 }
 
 }  // namespace pam

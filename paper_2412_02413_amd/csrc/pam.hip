@@ -302,25 +302,30 @@ hipError_t launch_fused(K kernel, int nw, size_t lds, size_t lds_max, const pam:
   return hipGetLastError();
 }
 
+// slots per stage of the fused-role kernels
+constexpr int kFusedKC = 64;
+
 template <int NSUB, int NPC>
 hipError_t launch_precx(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
   using namespace pam;
+  constexpr int KC = kFusedKC;
   const int N = a.N, NM = 256 * NPC;   // largest N served by this instantiation
   switch (precision) {
     case PAM_PREC_SPLIT_BF16:
-      return launch_fused(k3x_split<__bf16, 3, NSUB, NPC>, 8, k3x_split_lds<3, NSUB>(N), k3x_split_lds<3, NSUB>(NM), a,
-                          blocks, st);
+      return launch_fused(k3x_split<__bf16, 3, NSUB, NPC, KC>, 8, k3x_split_lds<3, NSUB, KC>(N),
+                          k3x_split_lds<3, NSUB, KC>(NM), a, blocks, st);
     case PAM_PREC_SPLIT_FP16:
-      return launch_fused(k3x_split<_Float16, 3, NSUB, NPC>, 8, k3x_split_lds<3, NSUB>(N),
-                          k3x_split_lds<3, NSUB>(NM), a, blocks, st);
+      return launch_fused(k3x_split<_Float16, 3, NSUB, NPC, KC>, 8, k3x_split_lds<3, NSUB, KC>(N),
+                          k3x_split_lds<3, NSUB, KC>(NM), a, blocks, st);
     case PAM_PREC_BF16:
-      return launch_fused(k3x_split<__bf16, 1, NSUB, NPC>, 8, k3x_split_lds<1, NSUB>(N), k3x_split_lds<1, NSUB>(NM), a,
-                          blocks, st);
+      return launch_fused(k3x_split<__bf16, 1, NSUB, NPC, KC>, 8, k3x_split_lds<1, NSUB, KC>(N),
+                          k3x_split_lds<1, NSUB, KC>(NM), a, blocks, st);
     case PAM_PREC_FP16:
-      return launch_fused(k3x_split<_Float16, 1, NSUB, NPC>, 8, k3x_split_lds<1, NSUB>(N),
-                          k3x_split_lds<1, NSUB>(NM), a, blocks, st);
+      return launch_fused(k3x_split<_Float16, 1, NSUB, NPC, KC>, 8, k3x_split_lds<1, NSUB, KC>(N),
+                          k3x_split_lds<1, NSUB, KC>(NM), a, blocks, st);
     default:
-      return launch_fused(k3x_fp32<NSUB, NPC>, 8, k3x_fp32_lds<NSUB>(N), k3x_fp32_lds<NSUB>(NM), a, blocks, st);
+      return launch_fused(k3x_fp32<NSUB, NPC, KC>, 8, k3x_fp32_lds<NSUB, KC>(N), k3x_fp32_lds<NSUB, KC>(NM), a,
+                          blocks, st);
   }
 }
 
