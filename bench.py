@@ -403,6 +403,11 @@ def main():
             sur = surrogate_entry(geom, rf, main_res["images"], fps, args.precision, args.steps, args.warmup,
                                   args.surrogate)
             log(f"surrogate: {sur}")
+            if args.precision != "split_bf16":
+                # the same network on a split-BF16 full-aperture propagation (fallback in split BF16)
+                sur["with_split_bf16_propagation"] = surrogate_entry(
+                    geom, rf, main_res["images"], fps, "split_bf16", args.steps, args.warmup, args.surrogate)
+                log(f"surrogate, split BF16 propagation: {sur['with_split_bf16_propagation']}")
         else:
             log(f"surrogate weights not found at {args.surrogate}: no surrogate entry")
     pcie = pcie_inclusive(geom, rf_host, args.precision, max(3, args.steps // 4), dev)

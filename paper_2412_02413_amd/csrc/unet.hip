@@ -21,8 +21,9 @@ inline pam_status_t launched() { return hipGetLastError() == hipSuccess ? PAM_OK
 // channels, K = 9 taps x k_in channels.  Each lane gathers the 8 channels of
 // its pixel (shifted by the tap, zero outside the image) straight from the
 // NHWC tensor (16 contiguous bytes) and 8 weights of its output channel from
-// the [n_out][9][k_in] layout (16 contiguous bytes).  One wave per 32x32 tile,
-// four waves (four pixel tiles) per workgroup.
+// the [n_out][9][k_in] layout (16 contiguous bytes).  One wave per 32 pixels x
+// 32 NT output channels (each input fragment feeds NT products), four waves
+// (four pixel tiles) per workgroup.
 // ---------------------------------------------------------------------------
 struct ConvArgs {
   const bf16* x;
@@ -33,21 +34,24 @@ struct ConvArgs {
   int32_t ldx, h, w, k_in, ldy, n_out, relu, flip, acc;
 };
 
+template <int NT>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t tile = (int64_t)blockIdx.x * 4 + wv;
   const int64_t p0 = tile * 32;
   if (p0 >= a.P) return;  // wave-uniform; the kernel has no barriers
-  const int co0 = blockIdx.y * 32;
+  const int co0 = blockIdx.y * 32 * NT;
   const int i = lane & 31, half = lane >> 5;
   const int64_t p = p0 + i;
   const int wc = (int)(p % a.w);
   const int64_t r = p / a.w;
   const int hr = (int)(r % a.h);
   const int64_t img = r / a.h;
-  v16f C;
+  v16f C[NT];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) C[v] = 0.f;
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) C[n][v] = 0.f;
   const v8bf zero = {};
   for (int t = 0; t < 9; ++t) {
     int dh = t / 3 - 1, dw = t % 3 - 1;
@@ -59,25 +63,34 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     const bool valid = hh >= 0 && hh < a.h && ww >= 0 && ww < a.w;
     const bf16* xr = a.x + ((img * a.h + (valid ? hh : 0)) * a.w + (valid ? ww : 0)) * (int64_t)a.ldx + 8 * half;
     const bf16* wr = a.wt + ((int64_t)(co0 + i) * 9 + t) * a.k_in + 8 * half;
+    const int64_t wstep = (int64_t)32 * 9 * a.k_in;   // next 32 output channels
+    // each input fragment feeds NT output tiles
+#pragma unroll 2
     for (int k0 = 0; k0 < a.k_in; k0 += 16) {
       const v8bf av = valid ? *reinterpret_cast<const v8bf*>(xr + k0) : zero;
-      const v8bf bv = *reinterpret_cast<const v8bf*>(wr + k0);
-      C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, C, 0, 0, 0);
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const v8bf bv = *reinterpret_cast<const v8bf*>(wr + n * wstep + k0);
+        C[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, C[n], 0, 0, 0);
+      }
     }
   }
-  const int co = co0 + i;
-  const float bb = (a.bias && !a.acc) ? a.bias[co] : 0.f;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int row = 8 * (v >> 2) + 4 * half + (v & 3);
-    bf16* dst = a.y + (p0 + row) * (int64_t)a.ldy + co;
-    float val = C[v] + bb;
-    if (a.acc) {
-      val += (float)*dst;
-    } else if (a.relu) {
-      val = fmaxf(val, 0.f);
+  for (int n = 0; n < NT; ++n) {
+    const int co = co0 + 32 * n + i;
+    const float bb = (a.bias && !a.acc) ? a.bias[co] : 0.f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = 8 * (v >> 2) + 4 * half + (v & 3);
+      bf16* dst = a.y + (p0 + row) * (int64_t)a.ldy + co;
+      float val = C[n][v] + bb;
+      if (a.acc) {
+        val += (float)*dst;
+      } else if (a.relu) {
+        val = fmaxf(val, 0.f);
+      }
+      *dst = (bf16)val;
     }
-    *dst = (bf16)val;
   }
 }
 
@@ -433,8 +446,14 @@ pam_status_t pam_nn_conv3x3(const void* x, int32_t ldx, int32_t batch, int32_t h
   ConvArgs a{static_cast<const bf16*>(x), static_cast<const bf16*>(wt), bias, static_cast<bf16*>(y),
              (int64_t)batch * h * w, ldx, h, w, k_in, ldy, n_out, relu, flip, accumulate};
   const int64_t tiles = a.P / 32;
-  hipLaunchKernelGGL(conv3x3_kernel, dim3(blocks_for(tiles, 4), n_out / 32), dim3(256), 0,
-                     static_cast<hipStream_t>(hip_stream), a);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // 32 pixels x 32 NT output channels per wave
+  if (n_out % 128 == 0)
+    hipLaunchKernelGGL(conv3x3_kernel<4>, dim3(blocks_for(tiles, 4), n_out / 128), dim3(256), 0, st, a);
+  else if (n_out % 64 == 0)
+    hipLaunchKernelGGL(conv3x3_kernel<2>, dim3(blocks_for(tiles, 4), n_out / 64), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(conv3x3_kernel<1>, dim3(blocks_for(tiles, 4), n_out / 32), dim3(256), 0, st, a);
   return launched();
 }
 
