@@ -6,7 +6,8 @@
  * so that the image I = rho_n^2 * E of Eq. 11 can be formed from one propagation
  * instead of three.  It is a U-Net: 3x3 convolutions, 2x2 max pooling, nearest
  * 2x upsampling, channel concatenation, a 1x1 head with a mask output and a
- * predicted-error (confidence) output, an L1 loss and Adam.
+ * predicted-error (confidence) output, energy-weighted binary cross-entropy losses
+ * for the mask and the error head, and Adam.
  *
  * Conventions
  *   Activations: BF16, NHWC ([batch][h][w][channels], channels fastest) with a

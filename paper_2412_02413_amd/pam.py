@@ -189,12 +189,46 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def check_buffers(info, rf, image, nncc=None, rho_pairs=None, workspace=None, n_t=None) -> None:
+    """Reject buffers the C-ABI cannot check itself (it sees raw pointers): every tensor must
+    be a contiguous tensor on the plan's GPU, rf float32 [F][L][n_t], image and nncc float32
+    [F][n_z][N_x], rho_pairs float32 [F][n_pairs][n_z][N_x].  Raises PamError before any launch."""
+    import torch
+
+    def bad(msg):
+        raise PamError(PAM_ERR_INVALID_ARG, f"pam_as_tax: {msg}")
+
+    if rf is None or image is None:
+        bad("rf and image are required")
+    if rf.dim() != 3:
+        bad(f"rf must be [F][L][n_t], got shape {tuple(rf.shape)}")
+    F = int(rf.shape[0])
+    n_t = int(rf.shape[-1]) if n_t is None else int(n_t)
+    want = {"rf": (rf, (F, info.n_elements, n_t)), "image": (image, (F, info.n_z, info.n_x))}
+    if nncc is not None:
+        want["nncc"] = (nncc, (F, info.n_z, info.n_x))
+    if rho_pairs is not None:
+        want["rho_pairs"] = (rho_pairs, (F, info.n_pairs, info.n_z, info.n_x))
+    for name, (t, shape) in want.items():
+        if t.dtype != torch.float32:
+            bad(f"{name} must be float32, got {t.dtype}")
+        if tuple(t.shape) != shape:
+            bad(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+    tensors = [t for t, _ in want.values()] + ([workspace] if workspace is not None else [])
+    for t in tensors:
+        if not t.is_contiguous():
+            bad("every buffer must be contiguous")
+        if t.device.type != "cuda" or t.device.index != info.device:
+            bad(f"every buffer must live on cuda:{info.device}, got {t.device}")
+
+
 def pam_as_tax(plan: Plan, rf, image, nncc=None, rho_pairs=None, workspace=None, stream=None,
                n_t: Optional[int] = None) -> None:
     """Enqueue one reconstruction of rf [F][L][n_t] (device float32) on `stream`."""
     import torch
     F = int(rf.shape[0])
     n_t = int(rf.shape[-1]) if n_t is None else n_t
+    check_buffers(plan.info, rf, image, nncc, rho_pairs, workspace, n_t)
     if stream is None:
         stream = torch.cuda.current_stream(rf.device)
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
@@ -213,6 +247,7 @@ def pam_as_tax_events(plan: Plan, rf, image, events, nncc=None, rho_pairs=None, 
     import torch
     F = int(rf.shape[0])
     n_t = int(rf.shape[-1]) if n_t is None else n_t
+    check_buffers(plan.info, rf, image, nncc, rho_pairs, workspace, n_t)
     if stream is None:
         stream = torch.cuda.current_stream(rf.device)
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()

@@ -84,3 +84,25 @@ def test_valid_geometry_without_gpu_reports_device_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert plan_status(synth.cfg1_geometry()) == P.PAM_ERR_DEVICE
+
+
+def test_binding_buffer_checks_on_cpu():
+    """check_buffers rejects a wrong channel count, a short image, a non-float32 RF, a
+    non-contiguous view and (here) host tensors, each before any library call."""
+    import torch
+    info = P.PlanInfoC(n_bins=205, n_z=151, n_x=128, n_sub=3, n_elements=64, n_samples=1024, n_pairs=3,
+                       device=0)
+    rf = torch.zeros((2, 64, 1024))
+    img = torch.zeros((2, 151, 128))
+    cases = [
+        (torch.zeros((2, 63, 1024)), img, None),
+        (rf, torch.zeros((2, 150, 128)), None),
+        (rf.double(), img, None),
+        (rf, torch.zeros((2, 128, 151)).transpose(1, 2), None),
+        (rf, img, torch.zeros((2, 1, 151, 128))),
+        (rf, img, None),                                   # right shapes, but not on the GPU
+    ]
+    for r, i, pairs in cases:
+        with pytest.raises(P.PamError) as ei:
+            P.check_buffers(info, r, i, None, pairs, None)
+        assert ei.value.status == P.PAM_ERR_INVALID_ARG

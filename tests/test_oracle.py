@@ -365,3 +365,69 @@ def test_uneven_sources_soft():
     assert 0.15 < rpi_as < 0.4
     assert 0.6 * rpi_as < rpi_tax <= rpi_as * 1.0001
     assert rpi_as3 < 0.3 * rpi_as
+
+
+# ---------------------------------------------------------------- hand-worked values (reading of Eq. 4 text, Eq. 10, Eq. 12-13)
+
+def test_bins_exclude_dc_and_nyquist():
+    # a closed band covering [0, fs/2] keeps every bin except DC (k = 0) and Nyquist (k = n_t/2)
+    for n_t in (32, 1024):
+        ks = O.bins(20e6, n_t, [(0.0, 10e6)])
+        assert len(ks) == n_t // 2 - 1
+        assert ks[0] == 1 and ks[-1] == n_t // 2 - 1
+    # a band holding only the Nyquist frequency is empty
+    assert len(O.bins(20e6, 64, [(10e6, 10e6)])) == 0
+
+
+def test_weight_floor_and_cap_hand_values():
+    # every pair clamped to [eps, 1] before the cube root of Eq. 10:
+    #   (0.5, 0.25, 5e-4) -> (0.5, 0.25, 1e-3): cube root of 1.25e-4 = 0.05
+    #   (1.2, 0.5, 0.8)   -> (1, 0.5, 0.8):     cube root of 0.4
+    rho = np.array([[0.5, 1.2], [0.25, 0.5], [5e-4, 0.8]])
+    w = O.weight(rho, 1e-3, 3)
+    assert abs(w[0] - 0.05) < 1e-15
+    assert abs(w[1] - 0.7368062997280773) < 1e-15
+    # one pair (n = 2): capped, floored (also a negative pair), passed through
+    np.testing.assert_array_equal(O.weight(np.array([[1.5, -0.3, 0.42]]), 1e-3, 2), [1.0, 1e-3, 0.42])
+
+
+def test_ncc_zero_denominator_hand_values():
+    # pixel 0: S_1 = 0, so the pairs holding sub-aperture 1 are 0 (then floored to eps);
+    #          rho_23 = 2 / (sqrt(2) sqrt(8)) = 0.5
+    # pixel 1: 3 / (2 * 3) = 0.5, -1.5 / (3 * 1) = -0.5, 1 / (1 * 2) = 0.5
+    S = np.array([[0.0, 4.0], [2.0, 9.0], [8.0, 1.0]])
+    C = np.array([[0.0, 3.0], [2.0, -1.5], [0.0, 1.0]])
+    rho = O.ncc(S, C, np.array([(0, 1), (1, 2), (2, 0)]))
+    assert np.all(np.isfinite(rho))
+    np.testing.assert_allclose(rho, [[0.0, 0.5], [0.5, -0.5], [0.0, 0.5]], rtol=0, atol=1e-15)
+
+
+def test_dead_subaperture_closed_form():
+    """a_1 = a_2 = every element, a_3 = none.  S_3 = 0, so rho_23 = rho_31 = 0 and both are
+    floored to eps; rho_12 = 1 wherever S_1 > 0.  The TAX weight is (1 eps eps)^(1/3) =
+    eps^(2/3) = 0.01 at every pixel, rho_n = 1, and I = E = sum |2 p|^2 = 4 E_AS."""
+    g = small_cfg1(n_depths=9)
+    rf = synth.cfg1_frame(15)
+    apod = np.stack([np.ones(64), np.ones(64), np.zeros(64)]).astype(np.uint8)
+    r = O.as_tax(rf, g.replace(apod=apod))
+    assert np.all(r["S"][2] == 0.0)
+    np.testing.assert_array_equal(r["rho"][1:], 0.0)
+    np.testing.assert_allclose(r["rho"][0], 1.0, atol=1e-12)
+    np.testing.assert_allclose(r["w"], 0.01, rtol=1e-12)
+    np.testing.assert_allclose(r["rho_n"], 1.0, rtol=1e-12)
+    np.testing.assert_allclose(r["I"], 4 * O.as_image(rf, g), rtol=1e-11)
+
+
+def test_esa_isnr_centroid_hand_image():
+    I = np.array([[4.0, 1.0, 0.0, 0.0],
+                  [3.0, 2.5, 0.0, 0.0],
+                  [0.0, 0.0, 0.0, 1.0],
+                  [2.0, 0.0, 0.0, 1.0]])
+    # A_0.5 = pixels strictly above half the maximum (2): {4, 3, 2.5}; the pixel equal to 2 is outside
+    assert O.esa(I, 0.1e-3, 0.2e-3) == pytest.approx(3 * 0.1e-3 * 0.2e-3, rel=1e-14)
+    # Eq. 12: inside mean 9.5 / 3, outside mean (1 + 1 + 1 + 2) / 13 -> 10 log10(9.5 * 13 / 15)
+    assert abs(O.isnr_db(I) - 9.155756985400032) < 1e-12
+    # Eq. 13 with alpha = 0.7: pixels above 7 are (z0, x1) = 10 and (z0, x2) = 8
+    J = np.array([[0.0, 10.0, 8.0], [0.0, 0.0, 0.0]])
+    cx, cz = O.centroid(J, np.array([0.0, 1.0, 2.0]), np.array([5.0, 6.0]), 0.7)
+    assert abs(cx - 1.4444444444444444) < 1e-15 and cz == 5.0

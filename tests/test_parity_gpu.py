@@ -273,3 +273,45 @@ def test_band_union(pam, torch_cuda, cfg1_batch):
     res = run(pam, torch_cuda, g, cfg1_batch[:1])
     assert len(res["bins"]) == len(O.bins(g.fs_hz, g.n_samples, g.bands_hz))
     check_end_to_end(res, O.as_tax(cfg1_batch[0], g))
+
+
+@pytest.mark.parametrize("case", ["dead_third", "identical"])
+def test_degenerate_masks(pam, torch_cuda, case):
+    """Degenerate apodization sets against the oracle.  dead_third: a_3 is empty, so S_3 = 0
+    and the two pairs that hold it have a zero denominator (0, then the eps floor); the
+    weight is eps^(2/3) everywhere.  identical: a_1 = a_2 = a_3, so every pair reaches the
+    upper clamp and rho_n = 1."""
+    g = synth.cfg1_geometry().replace(depths_m=(24.0 + 0.2 * np.arange(37)) * MM)
+    rf = synth.batch(synth.cfg1_frame, [16])
+    ones, zeros = np.ones(64, np.uint8), np.zeros(64, np.uint8)
+    apod = np.stack([ones, ones, zeros]) if case == "dead_third" else np.stack([ones, ones, ones])
+    gg = g.replace(apod=apod)
+    res = run(pam, torch_cuda, gg, rf)
+    ref = O.as_tax(rf[0], gg)
+    check_end_to_end(res, ref)
+    np.testing.assert_allclose(res["rho_pairs"][0], ref["rho"], atol=TOL_RHO)
+    np.testing.assert_allclose(res["nncc"][0], 1.0, atol=TOL_RHO)
+    if case == "dead_third":
+        np.testing.assert_array_equal(res["rho_pairs"][0][1:], 0.0)
+
+
+def test_binding_rejects_misshaped_buffers(pam, torch_cuda):
+    """The binding checks device, dtype, contiguity and shape against the plan before any
+    launch: a wrong channel count or a short image is rejected and nothing is written."""
+    torch = torch_cuda
+    g = synth.cfg1_geometry()
+    plan = pam.pam_plan(g, 0)
+    try:
+        ws = pam.alloc_workspace(plan, 1)
+        img = torch.full((1, g.n_z, g.n_x), -7.0, device="cuda")
+        with pytest.raises(pam.PamError):
+            pam.pam_as_tax(plan, torch.zeros((1, 63, 1024), device="cuda"), img, workspace=ws)
+        with pytest.raises(pam.PamError):
+            pam.pam_as_tax(plan, torch.zeros((1, 64, 1024), device="cuda"), img[:, :-1], workspace=ws)
+        with pytest.raises(pam.PamError):
+            pam.pam_as_tax(plan, torch.zeros((1, 64, 1024), device="cuda", dtype=torch.float64), img,
+                           workspace=ws)
+        torch.cuda.synchronize()
+        assert bool((img == -7.0).all())
+    finally:
+        pam.pam_destroy(plan)
