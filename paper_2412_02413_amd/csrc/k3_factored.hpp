@@ -1,0 +1,427 @@
+// K3 with the inverse lateral transform factored into two matrix-core DFT stages.
+//
+// The fields of one (frame, bin, depth) are p_i(x) = sum_q A_i(q) e^{+2 pi i q x / N},
+// A_i(q) = H(q, z) G_i(q), with G_i the sub-aperture's lateral spectrum already
+// divided by N (K2) and H the propagator of Eq. 2.  With N = N1 N2, q = N2 q1 + q2 and
+// x = x1 + N1 x2 the kernel of the sum splits as
+//     e^{2 pi i q1 x1 / N1} e^{2 pi i q2 x1 / N} e^{2 pi i q2 x2 / N2},
+// so the transform is
+//   stage 1  Y(x1, q2)  = sum_q1 A(N2 q1 + q2) e^{2 pi i q1 x1 / N1}   (N1-point DFTs)
+//   twiddle  Y'(x1, q2) = Y(x1, q2) e^{2 pi i q2 x1 / N}
+//   stage 3  p(x1 + N1 x2) = sum_q2 Y'(x1, q2) e^{2 pi i q2 x2 / N2}  (N2-point DFTs)
+// Both DFT stages are complex GEMMs on the matrix cores against a constant 16-point
+// DFT matrix in real form: rows (output index, re/im) = 32, K = (input index, re/im)
+// = 32, and 32 independent transforms as the columns of one 32x32 tile.  Executed
+// matrix flops per complex output are 2 x 128 instead of the 4N of a dense DFT.
+//
+// This file serves N = 256 (N1 = N2 = 16).  A wave owns two depths and the full
+// 256 columns: its stage-1 tile has columns (q2, depth) = 16 x 2, its stage-3 tile
+// columns (x1, depth) = 16 x 2.  Between the stages each wave transposes its own
+// twiddled stage-1 results through a private LDS buffer (no workgroup barrier).
+// The accumulators of its 512 pixels (8 per lane) stay in registers over the bins.
+// A workgroup is 8 waves = 16 depths of one frame; it stages each bin's
+// coefficients and kz row in LDS (double-buffered, one barrier per bin).
+//
+// Matrix-core operand layouts (lane l, h = l / 32, c = l % 32):
+//   v_mfma_f32_32x32x2_f32:        A[c][2t + h],  B[2t + h][c],  t = 0..15 (k-steps)
+//   v_mfma_f32_32x32x16_{bf16,f16}: A[c][16s + 8h + j], B[16s + 8h + j][c], s = 0..1, j = 0..7
+//   result, register v = 0..15:     C[8(v/4) + 4h + v%4][c]
+// K index <-> (input index m, re/im): FP32 k = 2t + h <-> m = 8h + t/2, re/im = t%2;
+// 16-bit k = 16s + 8h + j <-> m = 8h + 4s + j/2, re/im = j%2.  Either way lane half h
+// supplies the inputs m = 8h..8h+7 of its column, re and im.  Output rows are
+// (x, re/im) = x + 16 (re/im), so register v < 8 holds Re and v + 8 Im of output
+// x = 8(v/4) + 4h + v%4.
+#pragma once
+#include "k3_fields_fused.hpp"
+
+namespace pam {
+
+constexpr int kFfN1 = 16;                 // stage-1 radix (and stage-3 radix at N = 256)
+constexpr int kFfRow = 18;                // float2 pitch of a staged / transposed row of 16
+constexpr int kFfZz = 16 * kFfRow + 16;   // float2 pitch of one depth's 16 rows in the transpose buffer
+constexpr int kFfWaves = 8;               // waves per workgroup (2 depths each)
+constexpr int kFfDepths = 2 * kFfWaves;   // depths per workgroup
+
+// Staged inputs of one bin: G [NSUB][16 q2][kFfRow] float2 then kz [16 q2][kFfRow] doubles.
+template <int NSUB>
+__host__ __device__ constexpr int ff_stage_f2() { return (NSUB + 1) * 16 * kFfRow; }
+// Transpose buffer of one wave: [NSUB][2 depths][kFfZz] float2.
+template <int NSUB>
+__host__ __device__ constexpr int ff_tr_f2() { return NSUB * 2 * kFfZz; }
+template <int NSUB>
+inline size_t k3ff_lds() {
+  return (size_t)(2 * ff_stage_f2<NSUB>() + kFfWaves * ff_tr_f2<NSUB>()) * sizeof(float2);
+}
+
+// Workgroup index -> (frame, depth tile, bin split).  Consecutive workgroups are
+// dispatched round-robin over the 8 XCDs; the remap gives each XCD a contiguous
+// range of logical indices, so the workgroups of one frame (which read the same
+// per-bin coefficients) share one L2.
+struct WgFF {
+  int sp, dt, f, b_begin, b_end;
+  __device__ WgFF(const K3Args& a) {
+    const int G = gridDim.x;
+    int bid = blockIdx.x;
+    if ((G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
+    sp = bid % a.n_split; bid /= a.n_split;
+    dt = bid % a.n_dt;    bid /= a.n_dt;
+    f = bid;
+    b_begin = sp * a.bins_per_split;
+    b_end = min(a.n_sel, b_begin + a.bins_per_split);
+  }
+};
+
+// One 16-byte piece of a bin's staged inputs per thread (512 threads cover NSUB <= 3).
+template <int NSUB>
+struct FfPiece {
+  uint4 v;
+  bool on;
+  int dst;   // float2 offset in the stage buffer
+  __device__ FfPiece(int tid) {
+    constexpr int ng = NSUB * 128;                 // pieces of G (2 complex each)
+    on = tid < ng + 128;
+    if (tid < ng) {
+      const int e = 2 * tid, i = e >> 8, q2 = (e >> 4) & 15, q1 = e & 15;
+      dst = (i * 16 + q2) * kFfRow + q1;
+    } else {
+      const int e = 2 * (tid - ng), q2 = e >> 4, q1 = e & 15;
+      dst = NSUB * 16 * kFfRow + q2 * kFfRow + q1;          // doubles at float2 granularity
+    }
+  }
+  __device__ __forceinline__ void load(const K3Args& a, int f, int b, int tid) {
+    constexpr int ng = NSUB * 128;
+    if (!on) return;
+    if (tid < ng)
+      v = *reinterpret_cast<const uint4*>(a.coeffs + ((size_t)f * a.n_sel + b) * NSUB * 256 + 2 * tid);
+    else
+      v = *reinterpret_cast<const uint4*>(a.kz_ff + (size_t)b * 256 + 2 * (tid - ng));
+  }
+  __device__ __forceinline__ void store(float2* stage) const {
+    if (on) *reinterpret_cast<uint4*>(stage + dst) = v;
+  }
+};
+
+// Operands of the constant 16-point DFT matrix for this lane (plan tables in lane order).
+template <typename T, int PASSES>
+struct FfConst;
+template <int PASSES>
+struct FfConst<float, PASSES> {
+  float w[16];
+  __device__ FfConst(const K3Args& a, int lane) {
+    const float4* src = reinterpret_cast<const float4*>(a.ff_w32) + lane * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 q = src[k];
+      w[4 * k] = q.x;
+      w[4 * k + 1] = q.y;
+      w[4 * k + 2] = q.z;
+      w[4 * k + 3] = q.w;
+    }
+  }
+};
+
+// Twiddles e^{2 pi i q2 x1 / 256} / 16 of this lane's 8 stage-1 outputs.
+struct FfTw {
+  float2 t[8];
+  __device__ FfTw(const K3Args& a, int lane) {
+    const float4* src = reinterpret_cast<const float4*>(a.ff_tw) + lane * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 q = src[k];
+      t[2 * k] = make_float2(q.x, q.y);
+      t[2 * k + 1] = make_float2(q.z, q.w);
+    }
+  }
+};
+
+template <int NSUB>
+__device__ __forceinline__ void ff_fold(const v16f (&C)[NSUB], float inv, float (&accS)[NSUB][8],
+                                        float (&accC)[AccCount<NSUB>::pairs > 0 ? AccCount<NSUB>::pairs : 1][8]) {
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    float pr[NSUB], pim[NSUB];
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) {
+      pr[i] = C[i][v] * inv;
+      pim[i] = C[i][v + 8] * inv;
+      accS[i][v] = fmaf(pr[i], pr[i], fmaf(pim[i], pim[i], accS[i][v]));
+    }
+    if constexpr (NSUB == 3) {
+      accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
+      accC[1][v] = fmaf(pr[1], pr[2], fmaf(pim[1], pim[2], accC[1][v]));
+      accC[2][v] = fmaf(pr[2], pr[0], fmaf(pim[2], pim[0], accC[2][v]));
+    } else if constexpr (NSUB == 2) {
+      accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
+    }
+  }
+}
+
+// Lane (c, h) of a wave holds depth d0 + c/16 and columns x = c%16 + 16 x2,
+// x2 = 8(v/4) + 4h + v%4 for v = 0..7.
+template <int NSUB>
+__device__ __forceinline__ void ff_store(const K3Args& a, int sp, int f, int d0, int lane,
+                                         const float (&accS)[NSUB][8],
+                                         const float (&accC)[AccCount<NSUB>::pairs > 0 ? AccCount<NSUB>::pairs : 1][8]) {
+  constexpr int NA = AccCount<NSUB>::total;
+  constexpr int NP = AccCount<NSUB>::pairs;
+  const int c = lane & 31, h = lane >> 5;
+  const int row = d0 + (c >> 4);
+  if (row >= a.n_z) return;
+  const size_t plane = (size_t)a.n_z * 256;
+  float* dst = a.accum + ((size_t)sp * a.F + f) * NA * plane + (size_t)row * 256 + (c & 15);
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int x = 16 * (8 * (v >> 2) + 4 * h + (v & 3));
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) dst[i * plane + x] = accS[i][v];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) dst[(NSUB + p) * plane + x] = accC[p][v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 operands on v_mfma_f32_32x32x2_f32.
+// ---------------------------------------------------------------------------
+template <int NSUB>
+__global__ __launch_bounds__(512, 1) void k3ff_fp32(K3Args a) {
+  constexpr int NP = AccCount<NSUB>::pairs;
+  extern __shared__ float2 lds2[];
+  float2* stage = lds2;                                          // [2][ff_stage_f2]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  float2* tr = lds2 + 2 * ff_stage_f2<NSUB>() + w * ff_tr_f2<NSUB>();
+  const WgFF wg(a);
+  const int f = wg.f;
+  const int c = lane & 31, h = lane >> 5;
+  const int q2 = c & 15, zz = c >> 4;                            // stage-1 column; also (x1, zz) of stage 3
+  const int d0 = wg.dt * kFfDepths + 2 * w;
+  const double z = d0 + zz < a.n_z ? a.z[d0 + zz] : -1.0;
+
+  const FfConst<float, 1> W(a, lane);
+  const FfTw tw(a, lane);
+  float accS[NSUB][8];
+  float accC[NP > 0 ? NP : 1][8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) accS[i][v] = 0.f;
+#pragma unroll
+    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
+  }
+
+  FfPiece<NSUB> pc(tid);
+  if (wg.b_begin < wg.b_end) {
+    pc.load(a, f, wg.b_begin, tid);
+    pc.store(stage);
+  }
+  __syncthreads();
+  for (int b = wg.b_begin; b < wg.b_end; ++b) {
+    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB>();
+    if (b + 1 < wg.b_end) pc.load(a, f, b + 1, tid);
+    const float inv = 16.0f * a.inv_scale[(size_t)f * a.n_sel + b];
+
+    // stage-1 operands: A_i(16 q1 + q2) for q1 = 8h..8h+7
+    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * kFfRow) + q2 * kFfRow + 8 * h;
+    float2 H[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) H[m] = z >= 0.0 ? propagator(z, kzr[m], a.zero_evanescent) : make_float2(0.f, 0.f);
+    float bv[NSUB][16];
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) {
+      const float4* g = reinterpret_cast<const float4*>(st + (i * 16 + q2) * kFfRow + 8 * h);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4 gg = g[k];
+        const float2 a0 = cmul(H[2 * k], make_float2(gg.x, gg.y));
+        const float2 a1 = cmul(H[2 * k + 1], make_float2(gg.z, gg.w));
+        bv[i][4 * k] = a0.x;
+        bv[i][4 * k + 1] = a0.y;
+        bv[i][4 * k + 2] = a1.x;
+        bv[i][4 * k + 3] = a1.y;
+      }
+    }
+    v16f C[NSUB];
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) C[i][v] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) C[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w[t], bv[i][t], C[i], 0, 0, 0);
+
+    // twiddle and transpose: Y'(x1, q2) -> tr[i][zz][x1][q2]
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int x1 = 8 * (v >> 2) + 4 * h + (v & 3);
+        tr[i * 2 * kFfZz + zz * kFfZz + x1 * kFfRow + q2] = cmul(make_float2(C[i][v], C[i][v + 8]), tw.t[v]);
+      }
+    __builtin_amdgcn_wave_barrier();
+    // stage-3 operands: Y'(x1, q2) for q2 = 8h..8h+7 of column (x1 = c%16, zz)
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) {
+      const float4* y = reinterpret_cast<const float4*>(tr + i * 2 * kFfZz + zz * kFfZz + q2 * kFfRow + 8 * h);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4 yy = y[k];
+        bv[i][4 * k] = yy.x;
+        bv[i][4 * k + 1] = yy.y;
+        bv[i][4 * k + 2] = yy.z;
+        bv[i][4 * k + 3] = yy.w;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) C[i][v] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) C[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w[t], bv[i][t], C[i], 0, 0, 0);
+    ff_fold<NSUB>(C, inv, accS, accC);
+
+    if (b + 1 < wg.b_end) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB>());
+    __syncthreads();
+  }
+  ff_store<NSUB>(a, wg.sp, f, d0, lane, accS, accC);
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit operands on v_mfma_f32_32x32x16_{bf16,f16}: each operand is split into
+// hi = T(x) and lo = T(x - hi); PASSES = 3 sums hi.hi + hi.lo + lo.hi, PASSES = 1
+// takes hi.hi only.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct FfSplit {
+  typedef typename Mma<T>::v8 v8;
+  // 8 floats -> hi and lo 16-bit vectors
+  static __device__ __forceinline__ void split(const float (&x)[8], v8& hi, v8& lo) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const T hj = (T)x[j];
+      hi[j] = hj;
+      lo[j] = (T)(x[j] - (float)hj);
+    }
+  }
+};
+
+template <typename T, int PASSES, int NSUB>
+__global__ __launch_bounds__(512, 1) void k3ff_split(K3Args a) {
+  typedef typename Mma<T>::v8 v8;
+  constexpr int NP = AccCount<NSUB>::pairs;
+  extern __shared__ float2 lds2[];
+  float2* stage = lds2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  float2* tr = lds2 + 2 * ff_stage_f2<NSUB>() + w * ff_tr_f2<NSUB>();
+  const WgFF wg(a);
+  const int f = wg.f;
+  const int c = lane & 31, h = lane >> 5;
+  const int q2 = c & 15, zz = c >> 4;
+  const int d0 = wg.dt * kFfDepths + 2 * w;
+  const double z = d0 + zz < a.n_z ? a.z[d0 + zz] : -1.0;
+
+  // constant DFT operands: [lane][s][hi 8 | lo 8] 16-bit
+  v8 Wh[2], Wl[2];
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(a.ff_w16) + lane * 4;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      Wh[s] = __builtin_bit_cast(v8, src[2 * s]);
+      Wl[s] = __builtin_bit_cast(v8, src[2 * s + 1]);
+    }
+  }
+  const FfTw tw(a, lane);
+  float accS[NSUB][8];
+  float accC[NP > 0 ? NP : 1][8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) accS[i][v] = 0.f;
+#pragma unroll
+    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
+  }
+
+  auto gemm = [&](const v8 (&bh)[NSUB][2], const v8 (&bl)[NSUB][2], v16f (&C)[NSUB]) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) C[i][v] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) {
+        C[i] = Mma<T>::run(Wh[s], bh[i][s], C[i]);
+        if (PASSES == 3) {
+          C[i] = Mma<T>::run(Wh[s], bl[i][s], C[i]);
+          C[i] = Mma<T>::run(Wl[s], bh[i][s], C[i]);
+        }
+      }
+  };
+
+  FfPiece<NSUB> pc(tid);
+  if (wg.b_begin < wg.b_end) {
+    pc.load(a, f, wg.b_begin, tid);
+    pc.store(stage);
+  }
+  __syncthreads();
+  for (int b = wg.b_begin; b < wg.b_end; ++b) {
+    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB>();
+    if (b + 1 < wg.b_end) pc.load(a, f, b + 1, tid);
+    const float inv = 16.0f * a.inv_scale[(size_t)f * a.n_sel + b];
+
+    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * kFfRow) + q2 * kFfRow + 8 * h;
+    float2 H[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) H[m] = z >= 0.0 ? propagator(z, kzr[m], a.zero_evanescent) : make_float2(0.f, 0.f);
+    v8 bh[NSUB][2], bl[NSUB][2];
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) {
+      const float4* g = reinterpret_cast<const float4*>(st + (i * 16 + q2) * kFfRow + 8 * h);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        float x[8];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const float4 gg = g[2 * s + k];
+          const float2 a0 = cmul(H[4 * s + 2 * k], make_float2(gg.x, gg.y));
+          const float2 a1 = cmul(H[4 * s + 2 * k + 1], make_float2(gg.z, gg.w));
+          x[4 * k] = a0.x;
+          x[4 * k + 1] = a0.y;
+          x[4 * k + 2] = a1.x;
+          x[4 * k + 3] = a1.y;
+        }
+        FfSplit<T>::split(x, bh[i][s], bl[i][s]);
+      }
+    }
+    v16f C[NSUB];
+    gemm(bh, bl, C);
+
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int x1 = 8 * (v >> 2) + 4 * h + (v & 3);
+        tr[i * 2 * kFfZz + zz * kFfZz + x1 * kFfRow + q2] = cmul(make_float2(C[i][v], C[i][v + 8]), tw.t[v]);
+      }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) {
+      const float4* y = reinterpret_cast<const float4*>(tr + i * 2 * kFfZz + zz * kFfZz + q2 * kFfRow + 8 * h);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const float4 y0 = y[2 * s], y1 = y[2 * s + 1];
+        const float x[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+        FfSplit<T>::split(x, bh[i][s], bl[i][s]);
+      }
+    }
+    gemm(bh, bl, C);
+    ff_fold<NSUB>(C, inv, accS, accC);
+
+    if (b + 1 < wg.b_end) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB>());
+    __syncthreads();
+  }
+  ff_store<NSUB>(a, wg.sp, f, d0, lane, accS, accC);
+}
+
+}  // namespace pam

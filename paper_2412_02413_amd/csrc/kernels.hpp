@@ -111,10 +111,11 @@ __global__ __launch_bounds__(256) void k1_time_fft(K1Args a) {
 }
 
 // --------------------------------------------------------------------------
-// K2: apodize, place on the lateral grid, lateral DFT, fold into slot order and
-// scale by a power of two (exact) so that the largest coefficient lies in
-// [2^11, 2^12): this keeps FP16 hi/lo splits of the products normal and is a
-// no-op on the results.  One workgroup per (bin, frame).
+// K2: apodize, place on the lateral grid, lateral DFT, fold into slot order (or,
+// for the factored transform, reorder the unfolded spectrum so that q = N2 q1 + q2
+// is stored at q2 N1 + q1) and scale by a power of two (exact) so that the largest
+// coefficient lies in [2^11, 2^12): this keeps FP16 hi/lo splits of the products
+// normal and is a no-op on the results.  One workgroup per (bin, frame).
 // --------------------------------------------------------------------------
 struct K2Args {
   const float2* spectra;  // [F][n_sel][L]
@@ -124,6 +125,7 @@ struct K2Args {
   const float* masks;     // [n_sub][L]
   int32_t L, N, n_sub, n_sel;
   int32_t col0, col_step; // grid column of element l is col0 + col_step * l
+  int32_t ff_n1;          // 0: folded slot order; N1 > 0: unfolded P(q)/N in [q2][q1] order, q = (N/N1) q1 + q2
 };
 
 template <int NSUB>
@@ -175,7 +177,10 @@ __global__ __launch_bounds__(256) void k2_lateral(K2Args a) {
     const int i = e / N, s = e - i * N, q = s >> 1;
     const float2* Pi = P + i * N;
     float2 g;
-    if ((s & 1) == 0) {
+    if (a.ff_n1 > 0) {
+      const int n2 = N / a.ff_n1;
+      g = Pi[n2 * (s % a.ff_n1) + s / a.ff_n1];   // s = q2 N1 + q1
+    } else if ((s & 1) == 0) {
       g = (q == 0) ? Pi[0] : cadd(Pi[q], Pi[N - q]);
     } else if (q == 0) {
       g = Pi[N / 2];
@@ -220,6 +225,11 @@ struct K3Args {
   const float* basis_lane; // [N/32 chunks][N x][2][16] basis in 32x32x2 operand order (fused FP32 kernel)
   float* accum;            // [n_split][F][n_acc][n_z][N]
   int32_t N, n_z, n_sel, F, n_dt, n_xg, n_split, bins_per_split, zero_evanescent;
+  // factored-transform kernels (k3_factored.hpp)
+  const double* kz_ff;     // [n_sel][N2][N1] signed kz / (2 pi) at q = N2 q1 + q2
+  const float* ff_w32;     // [64 lanes][16] 16-point DFT matrix, FP32 operand order
+  const void* ff_w16;      // [64 lanes][2 k-steps][hi 8, lo 8] 16-point DFT matrix, 16-bit operand order
+  const float2* ff_tw;     // [64 lanes][8] twiddles e^{2 pi i q2 x1 / N} / 16 of the lane's stage-1 outputs
 };
 
 template <int NSUB>

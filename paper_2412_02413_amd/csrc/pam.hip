@@ -14,6 +14,7 @@
 #include "k3_fields.hpp"
 #include "k3_fields16.hpp"
 #include "k3_fields_fused.hpp"
+#include "k3_factored.hpp"
 
 namespace {
 
@@ -42,6 +43,7 @@ struct Level {
   int n_sel = 0;
   int32_t* d_ksel = nullptr;  // bin k on the level's own grid
   double* d_kz = nullptr;     // [n_sel][kz_row(N)] signed kz / (2 pi) of the selected bins
+  double* d_kzff = nullptr;   // [n_sel][N2][N1] the same values at q = N2 q1 + q2 (factored kernels)
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -100,6 +102,10 @@ struct pam_plan_s {
   float* d_basis_lane = nullptr;  // [N/32][N][2][16]: the basis in matrix-core operand order
   uint16_t* d_bhi = nullptr;   // [N/8][N][8] basis (slot groups, x, slots), 16-bit hi (split kernels)
   uint16_t* d_blo = nullptr;   // same layout, 16-bit lo
+  bool ff = false;             // inverse lateral transform factored into two 16-point stages (N = 256)
+  float* d_ff_w32 = nullptr;   // [64][16] 16-point DFT matrix in FP32 operand order
+  uint16_t* d_ff_w16 = nullptr;  // [64][2][16] the same in 16-bit operand order, hi then lo per k-step
+  float2* d_ff_tw = nullptr;   // [64][8] twiddles / 16 in stage-1 output order
   std::vector<void*> allocs;
 };
 
@@ -180,7 +186,13 @@ LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
   s.xt = 1;
   s.ct = 0;
   s.fw = 0;
-  if (p->N == 256 || p->N == 512) {
+  if (p->ff) {
+    // 16 depths x all 256 columns per workgroup, 8 waves of 2 depths
+    s.fw = -1;
+    s.nw = pam::kFfWaves;
+    s.n_dt = (p->n_z + pam::kFfDepths - 1) / pam::kFfDepths;
+    s.n_xg = 1;
+  } else if (p->N == 256 || p->N == 512) {
     // 32 depths x 256 columns per workgroup, 8 waves each generating and multiplying
     s.fw = 8;
     s.nw = s.fw;
@@ -248,9 +260,11 @@ pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layou
 
 // K3 kernels: NC consumer + NC producer waves, NC*32 columns per workgroup.
 // LDS above 64 KiB needs the per-kernel attribute.
+// (Every kernel shares one signature, so the attribute is set per launch rather
+// than cached in a per-instantiation static.)
 template <typename K>
 hipError_t launch_with_lds(K kernel, int nc, size_t lds, const pam::K3Args& a, int blocks, hipStream_t st) {
-  static const hipError_t attr =
+  const hipError_t attr =
       hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(nc * 128), lds, st, a);
@@ -294,8 +308,8 @@ hipError_t launch_prec16(int precision, const pam::K3Args& a, int blocks, hipStr
 template <typename K>
 hipError_t launch_fused(K kernel, int nw, size_t lds, size_t lds_max, const pam::K3Args& a, int blocks,
                         hipStream_t st) {
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+  const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
   if (attr != hipSuccess) return attr;
   if (lds > lds_max) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(nw * 64), lds, st, a);
@@ -330,7 +344,21 @@ hipError_t launch_precx(int precision, const pam::K3Args& a, int blocks, hipStre
 }
 
 template <int NSUB>
+hipError_t launch_ff(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+  using namespace pam;
+  const size_t lds = k3ff_lds<NSUB>();
+  switch (precision) {
+    case PAM_PREC_SPLIT_BF16: return launch_fused(k3ff_split<__bf16, 3, NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_SPLIT_FP16: return launch_fused(k3ff_split<_Float16, 3, NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_BF16: return launch_fused(k3ff_split<__bf16, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_FP16: return launch_fused(k3ff_split<_Float16, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    default: return launch_fused(k3ff_fp32<NSUB>, kFfWaves, lds, lds, a, blocks, st);
+  }
+}
+
+template <int NSUB>
 hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
+  if (s.fw < 0) return launch_ff<NSUB>(precision, a, blocks, st);
   if (s.fw == 8) return a.N > 256 ? launch_precx<NSUB, 2>(precision, a, blocks, st)
                                    : launch_precx<NSUB, 1>(precision, a, blocks, st);
   if (s.ct == 4) return launch_prec16<NSUB, 4>(precision, a, blocks, st);
@@ -475,10 +503,55 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       }
   }
 
+  // Factored transform (N = 256 = 16 x 16): the 16-point DFT matrix W(x, m) = e^{2 pi i m x / 16}
+  // in real form, rows (x, re/im) = x + 16 ro, and the stage twiddles, all in lane order of
+  // the matrix-core operands.  Lane l: column c = l % 32, half h = l / 32.
+  p->ff = (N == 256);
+  std::vector<float> ff_w32;
+  std::vector<uint16_t> ff_w16;
+  std::vector<float2> ff_tw;
+  if (p->ff) {
+    auto wval = [](int row, int m, int ri) {
+      const int x = row % 16, ro = row / 16;
+      const double th = 2.0 * kPi * (double)((m * x) % 16) / 16.0;
+      const double c = std::cos(th), sn = std::sin(th);
+      return ro == 0 ? (ri == 0 ? c : -sn) : (ri == 0 ? sn : c);
+    };
+    ff_w32.resize(64 * 16);
+    ff_w16.resize(64 * 32);
+    ff_tw.resize(64 * 8);
+    const bool h16 = is_fp16(p->precision);
+    for (int l = 0; l < 64; ++l) {
+      const int c = l % 32, h = l / 32;
+      // FP32 k-step t: k = 2t + h <-> input m = 8h + t/2, re/im t%2
+      for (int t = 0; t < 16; ++t) ff_w32[l * 16 + t] = (float)wval(c, 8 * h + t / 2, t % 2);
+      // 16-bit k-step s, element j: k = 16s + 8h + j <-> m = 8h + 4s + j/2, re/im j%2
+      for (int s2 = 0; s2 < 2; ++s2)
+        for (int j = 0; j < 8; ++j) {
+          const float v = (float)wval(c, 8 * h + 4 * s2 + j / 2, j % 2);
+          const uint16_t hi = h16 ? to_fp16(v) : to_bf16(v);
+          const float r = v - (h16 ? from_fp16(hi) : from_bf16(hi));
+          ff_w16[l * 32 + s2 * 16 + j] = hi;
+          ff_w16[l * 32 + s2 * 16 + 8 + j] = h16 ? to_fp16(r) : to_bf16(r);
+        }
+      // stage-1 output v (0..7) of lane l is x1 = 8(v/4) + 4h + v%4 of column q2 = c % 16
+      for (int v = 0; v < 8; ++v) {
+        const int x1 = 8 * (v / 4) + 4 * h + v % 4, q2 = c % 16;
+        const double th = 2.0 * kPi * (double)((q2 * x1) % 256) / 256.0;
+        ff_tw[l * 8 + v] = make_float2((float)(std::cos(th) / 16.0), (float)(std::sin(th) / 16.0));
+      }
+    }
+  }
+
   do {
     if (is_split(p->precision)) {
       if ((st = upload(p, &p->d_bhi, bhi.data(), bhi.size())) != PAM_OK) break;
       if ((st = upload(p, &p->d_blo, blo.data(), blo.size())) != PAM_OK) break;
+    }
+    if (p->ff) {
+      if ((st = upload(p, &p->d_ff_w32, ff_w32.data(), ff_w32.size())) != PAM_OK) break;
+      if ((st = upload(p, &p->d_ff_w16, ff_w16.data(), ff_w16.size())) != PAM_OK) break;
+      if ((st = upload(p, &p->d_ff_tw, ff_tw.data(), ff_tw.size())) != PAM_OK) break;
     }
     if ((st = upload(p, &p->d_z, z.data(), z.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_tw, tw.data(), tw.size())) != PAM_OK) break;
@@ -502,6 +575,17 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       lv.n_sel = (int)ksel.size();
       if ((st = upload(p, &lv.d_ksel, ksel.data(), ksel.size())) != PAM_OK) break;
       if ((st = upload(p, &lv.d_kz, kz_lv.data(), kz_lv.size())) != PAM_OK) break;
+      if (p->ff) {
+        // [n_sel][q2][q1] at q = 16 q1 + q2; kz depends on q through min(q, N - q)
+        std::vector<double> kzff((size_t)lv.n_sel * N);
+        for (int b = 0; b < lv.n_sel; ++b)
+          for (int q2 = 0; q2 < 16; ++q2)
+            for (int q1 = 0; q1 < 16; ++q1) {
+              const int q = 16 * q1 + q2, qf = std::min(q, N - q);
+              kzff[(size_t)b * N + q2 * 16 + q1] = kz_lv[(size_t)b * pam::kz_row(N) + qf];
+            }
+        if ((st = upload(p, &lv.d_kzff, kzff.data(), kzff.size())) != PAM_OK) break;
+      }
       p->levels.push_back(lv);
     }
   } while (false);
@@ -588,7 +672,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   // K2: lateral DFT + fold, one workgroup per (bin, frame)
   {
     pam::K2Args a{spectra, coeffs, scales, p->d_twx, p->d_masks, p->L, p->N, p->n_sub, lv->n_sel,
-                  p->col0, p->col_step};
+                  p->col0, p->col_step, p->ff ? pam::kFfN1 : 0};
     const size_t lds = (size_t)(p->N + 3 * p->L + 2 * p->n_sub * p->N) * sizeof(float2);
     if (p->n_sub == 3)
       hipLaunchKernelGGL(pam::k2_lateral<3>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
@@ -602,7 +686,8 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   {
     const LaunchShape s = k3_shape(p, F, lv->n_sel);
     pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, p->d_basis_lane, accum,
-                  p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent};
+                  p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent,
+                  lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
     if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
     if (launch_k3(p->precision, p->n_sub, s, a, (int)blocks, stream) != hipSuccess || !mark(3))

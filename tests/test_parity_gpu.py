@@ -315,3 +315,17 @@ def test_binding_rejects_misshaped_buffers(pam, torch_cuda):
         assert bool((img == -7.0).all())
     finally:
         pam.pam_destroy(plan)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16", "split_fp16", "bf16"])
+@pytest.mark.parametrize("n_sub", [1, 2, 3])
+def test_factored_transform_forms(pam, torch_cuda, precision, n_sub):
+    """N = 256 (the factored two-stage transform) in every sub-aperture count and operand form,
+    two frames, 37 depths (three 16-depth tiles, ragged tail)."""
+    g = synth.cfg2_geometry()
+    g = g.replace(depths_m=g.depths_m[np.linspace(0, 511, 37).astype(int)], n_sub=n_sub)
+    rf = np.stack([synth.cfg2_frame(300 + s)[0] for s in range(2)])
+    res = run(pam, torch_cuda, g, rf, precision=precision, want_pairs=n_sub > 1)
+    tol_i, tol_rho = {"fp32": (TOL_I, TOL_RHO), "bf16": (1e-2, 5e-2)}.get(precision, SPLIT_TOL)
+    for f in range(2):
+        check_end_to_end(res, O.as_tax(rf[f], g), f, tol_i=tol_i, tol_rho=tol_rho)
