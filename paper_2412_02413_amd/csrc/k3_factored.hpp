@@ -32,6 +32,8 @@
 // (x, re/im) = x + 16 (re/im), so register v < 8 holds Re and v + 8 Im of output
 // x = 8(v/4) + 4h + v%4.
 #pragma once
+#include <type_traits>
+
 #include "k3_fields_fused.hpp"
 
 namespace pam {
@@ -101,26 +103,7 @@ struct FfPiece {
   }
 };
 
-// Operands of the constant 16-point DFT matrix for this lane (plan tables in lane order).
-template <typename T, int PASSES>
-struct FfConst;
-template <int PASSES>
-struct FfConst<float, PASSES> {
-  float w[16];
-  __device__ FfConst(const K3Args& a, int lane) {
-    const float4* src = reinterpret_cast<const float4*>(a.ff_w32) + lane * 4;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float4 q = src[k];
-      w[4 * k] = q.x;
-      w[4 * k + 1] = q.y;
-      w[4 * k + 2] = q.z;
-      w[4 * k + 3] = q.w;
-    }
-  }
-};
-
-// Twiddles e^{2 pi i q2 x1 / 256} / 16 of this lane's 8 stage-1 outputs.
+// Twiddles e^{2 pi i q2 x1 / 256} of this lane's 8 stage-1 outputs (/ 16 for FP16 operands).
 struct FfTw {
   float2 t[8];
   __device__ FfTw(const K3Args& a, int lane) {
@@ -133,28 +116,6 @@ struct FfTw {
     }
   }
 };
-
-template <int NSUB>
-__device__ __forceinline__ void ff_fold(const v16f (&C)[NSUB], float inv, float (&accS)[NSUB][8],
-                                        float (&accC)[AccCount<NSUB>::pairs > 0 ? AccCount<NSUB>::pairs : 1][8]) {
-#pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    float pr[NSUB], pim[NSUB];
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i) {
-      pr[i] = C[i][v] * inv;
-      pim[i] = C[i][v + 8] * inv;
-      accS[i][v] = fmaf(pr[i], pr[i], fmaf(pim[i], pim[i], accS[i][v]));
-    }
-    if constexpr (NSUB == 3) {
-      accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
-      accC[1][v] = fmaf(pr[1], pr[2], fmaf(pim[1], pim[2], accC[1][v]));
-      accC[2][v] = fmaf(pr[2], pr[0], fmaf(pim[2], pim[0], accC[2][v]));
-    } else if constexpr (NSUB == 2) {
-      accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
-    }
-  }
-}
 
 // Lane (c, h) of a wave holds depth d0 + c/16 and columns x = c%16 + 16 x2,
 // x2 = 8(v/4) + 4h + v%4 for v = 0..7.
@@ -180,11 +141,51 @@ __device__ __forceinline__ void ff_store(const K3Args& a, int sp, int f, int d0,
 }
 
 // ---------------------------------------------------------------------------
-// FP32 operands on v_mfma_f32_32x32x2_f32.
+// The kernel.  T = float: FP32 operands on v_mfma_f32_32x32x2_f32.  T = __bf16 or
+// _Float16: operands on v_mfma_f32_32x32x16_*, each split into hi = T(x) and
+// lo = T(x - hi); PASSES = 3 sums hi.hi + hi.lo + lo.hi, PASSES = 1 takes hi.hi.
+//
+// Per bin a wave runs a front half (propagator, stage-1 operands, stage-1
+// products, twiddle, transpose into its LDS buffer) and a back half (stage-3
+// operands from the buffer, stage-3 products, fold into the per-pixel sums).  The
+// two waves that share a SIMD (w and w + 4) are half a bin apart: waves 0-3 run
+// front(b) then back(b), waves 4-7 run back(b - 1) then front(b), so while one
+// wave's products occupy the matrix core the other runs its VALU and LDS work.
+//
+// Scale: for FP16 operands K2 scales each bin's coefficients by a power of two s and
+// the twiddles carry 1/16, so that both stages' operands stay in FP16 range; 16/s
+// then multiplies the fields in the fold.  FP32 and BF16 operands take s = 1 and
+// unscaled twiddles.
 // ---------------------------------------------------------------------------
-template <int NSUB>
-__global__ __launch_bounds__(512, 1) void k3ff_fp32(K3Args a) {
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct FfOps {
+  typedef typename Mma<T>::v8 v8;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ float widen(T h) { return (float)h; }
+  // 8 floats -> hi and lo 16-bit vectors, two values per conversion
+  static __device__ __forceinline__ void split(const float (&x)[8], v8& hi, v8& lo) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const v2f xx = {x[2 * j], x[2 * j + 1]};
+      const v2 hh = __builtin_convertvector(xx, v2);
+      const v2f back = __builtin_convertvector(hh, v2f);
+      const v2 ll = __builtin_convertvector(xx - back, v2);
+      hi[2 * j] = hh[0];
+      hi[2 * j + 1] = hh[1];
+      lo[2 * j] = ll[0];
+      lo[2 * j + 1] = ll[1];
+    }
+  }
+};
+
+template <typename T, int PASSES, int NSUB>
+__global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  constexpr bool SCALED = std::is_same<T, _Float16>::value;   // keep K2's scale through stage 3
   constexpr int NP = AccCount<NSUB>::pairs;
+  typedef typename std::conditional<F32, float, typename Mma<typename std::conditional<F32, __bf16, T>::type>::v8>::type v8;
   extern __shared__ float2 lds2[];
   float2* stage = lds2;                                          // [2][ff_stage_f2]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -192,138 +193,27 @@ __global__ __launch_bounds__(512, 1) void k3ff_fp32(K3Args a) {
   const WgFF wg(a);
   const int f = wg.f;
   const int c = lane & 31, h = lane >> 5;
-  const int q2 = c & 15, zz = c >> 4;                            // stage-1 column; also (x1, zz) of stage 3
+  const int q2 = c & 15, zz = c >> 4;                            // stage-1 column; (x1, zz) of stage 3
   const int d0 = wg.dt * kFfDepths + 2 * w;
-  const double z = d0 + zz < a.n_z ? a.z[d0 + zz] : -1.0;
+  // rows beyond the grid run with z = 0: their pixels stay in their own columns of
+  // both stages and are never stored
+  const double z = d0 + zz < a.n_z ? a.z[d0 + zz] : 0.0;
+  const bool lag = w >= 4;
 
-  const FfConst<float, 1> W(a, lane);
-  const FfTw tw(a, lane);
-  float accS[NSUB][8];
-  float accC[NP > 0 ? NP : 1][8];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) {
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i) accS[i][v] = 0.f;
-#pragma unroll
-    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
-  }
-
-  FfPiece<NSUB> pc(tid);
-  if (wg.b_begin < wg.b_end) {
-    pc.load(a, f, wg.b_begin, tid);
-    pc.store(stage);
-  }
-  __syncthreads();
-  for (int b = wg.b_begin; b < wg.b_end; ++b) {
-    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB>();
-    if (b + 1 < wg.b_end) pc.load(a, f, b + 1, tid);
-    const float inv = 16.0f * a.inv_scale[(size_t)f * a.n_sel + b];
-
-    // stage-1 operands: A_i(16 q1 + q2) for q1 = 8h..8h+7
-    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * kFfRow) + q2 * kFfRow + 8 * h;
-    float2 H[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) H[m] = z >= 0.0 ? propagator(z, kzr[m], a.zero_evanescent) : make_float2(0.f, 0.f);
-    float bv[NSUB][16];
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i) {
-      const float4* g = reinterpret_cast<const float4*>(st + (i * 16 + q2) * kFfRow + 8 * h);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float4 gg = g[k];
-        const float2 a0 = cmul(H[2 * k], make_float2(gg.x, gg.y));
-        const float2 a1 = cmul(H[2 * k + 1], make_float2(gg.z, gg.w));
-        bv[i][4 * k] = a0.x;
-        bv[i][4 * k + 1] = a0.y;
-        bv[i][4 * k + 2] = a1.x;
-        bv[i][4 * k + 3] = a1.y;
-      }
-    }
-    v16f C[NSUB];
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) C[i][v] = 0.f;
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-#pragma unroll
-      for (int i = 0; i < NSUB; ++i) C[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w[t], bv[i][t], C[i], 0, 0, 0);
-
-    // twiddle and transpose: Y'(x1, q2) -> tr[i][zz][x1][q2]
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i)
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int x1 = 8 * (v >> 2) + 4 * h + (v & 3);
-        tr[i * 2 * kFfZz + zz * kFfZz + x1 * kFfRow + q2] = cmul(make_float2(C[i][v], C[i][v + 8]), tw.t[v]);
-      }
-    __builtin_amdgcn_wave_barrier();
-    // stage-3 operands: Y'(x1, q2) for q2 = 8h..8h+7 of column (x1 = c%16, zz)
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i) {
-      const float4* y = reinterpret_cast<const float4*>(tr + i * 2 * kFfZz + zz * kFfZz + q2 * kFfRow + 8 * h);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float4 yy = y[k];
-        bv[i][4 * k] = yy.x;
-        bv[i][4 * k + 1] = yy.y;
-        bv[i][4 * k + 2] = yy.z;
-        bv[i][4 * k + 3] = yy.w;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < NSUB; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) C[i][v] = 0.f;
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-#pragma unroll
-      for (int i = 0; i < NSUB; ++i) C[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w[t], bv[i][t], C[i], 0, 0, 0);
-    ff_fold<NSUB>(C, inv, accS, accC);
-
-    if (b + 1 < wg.b_end) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB>());
-    __syncthreads();
-  }
-  ff_store<NSUB>(a, wg.sp, f, d0, lane, accS, accC);
-}
-
-// ---------------------------------------------------------------------------
-// 16-bit operands on v_mfma_f32_32x32x16_{bf16,f16}: each operand is split into
-// hi = T(x) and lo = T(x - hi); PASSES = 3 sums hi.hi + hi.lo + lo.hi, PASSES = 1
-// takes hi.hi only.
-// ---------------------------------------------------------------------------
-template <typename T>
-struct FfSplit {
-  typedef typename Mma<T>::v8 v8;
-  // 8 floats -> hi and lo 16-bit vectors
-  static __device__ __forceinline__ void split(const float (&x)[8], v8& hi, v8& lo) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const T hj = (T)x[j];
-      hi[j] = hj;
-      lo[j] = (T)(x[j] - (float)hj);
-    }
-  }
-};
-
-template <typename T, int PASSES, int NSUB>
-__global__ __launch_bounds__(512, 1) void k3ff_split(K3Args a) {
-  typedef typename Mma<T>::v8 v8;
-  constexpr int NP = AccCount<NSUB>::pairs;
-  extern __shared__ float2 lds2[];
-  float2* stage = lds2;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  float2* tr = lds2 + 2 * ff_stage_f2<NSUB>() + w * ff_tr_f2<NSUB>();
-  const WgFF wg(a);
-  const int f = wg.f;
-  const int c = lane & 31, h = lane >> 5;
-  const int q2 = c & 15, zz = c >> 4;
-  const int d0 = wg.dt * kFfDepths + 2 * w;
-  const double z = d0 + zz < a.n_z ? a.z[d0 + zz] : -1.0;
-
-  // constant DFT operands: [lane][s][hi 8 | lo 8] 16-bit
+  // constant 16-point DFT operands
+  float W32[16];
   v8 Wh[2], Wl[2];
-  {
+  if constexpr (F32) {
+    const float4* src = reinterpret_cast<const float4*>(a.ff_w32) + lane * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 q = src[k];
+      W32[4 * k] = q.x;
+      W32[4 * k + 1] = q.y;
+      W32[4 * k + 2] = q.z;
+      W32[4 * k + 3] = q.w;
+    }
+  } else {
     const uint4* src = reinterpret_cast<const uint4*>(a.ff_w16) + lane * 4;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -342,61 +232,85 @@ __global__ __launch_bounds__(512, 1) void k3ff_split(K3Args a) {
     for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
   }
 
-  auto gemm = [&](const v8 (&bh)[NSUB][2], const v8 (&bl)[NSUB][2], v16f (&C)[NSUB]) {
+  // products of one stage: C_i = W x operand_i for every sub-aperture
+  auto gemm = [&](const float (&bf)[NSUB][16], const v8 (&bh)[NSUB][2], const v8 (&bl)[NSUB][2],
+                  v16f (&C)[NSUB]) {
+    // the first product of each chain takes a zero accumulator (an inline constant)
+    const v16f zero = {};
+    if constexpr (F32) {
 #pragma unroll
-    for (int i = 0; i < NSUB; ++i)
+      for (int t = 0; t < 16; ++t)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) C[i][v] = 0.f;
+        for (int i = 0; i < NSUB; ++i)
+          C[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(W32[t], bf[i][t], t == 0 ? zero : C[i], 0, 0, 0);
+    } else {
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int i = 0; i < NSUB; ++i) {
-        C[i] = Mma<T>::run(Wh[s], bh[i][s], C[i]);
-        if (PASSES == 3) {
-          C[i] = Mma<T>::run(Wh[s], bl[i][s], C[i]);
-          C[i] = Mma<T>::run(Wl[s], bh[i][s], C[i]);
+        for (int i = 0; i < NSUB; ++i) {
+          C[i] = Mma<T>::run(Wh[s], bh[i][s], s == 0 ? zero : C[i]);
+          if (PASSES == 3) {
+            C[i] = Mma<T>::run(Wh[s], bl[i][s], C[i]);
+            C[i] = Mma<T>::run(Wl[s], bh[i][s], C[i]);
+          }
         }
+    }
+  };
+  // 16 operand values (inputs m = 8h..8h+7, re/im) of sub-aperture i into the operand registers
+  auto put = [&](int i, const float (&x)[16], float (&bf)[NSUB][16], v8 (&bh)[NSUB][2], v8 (&bl)[NSUB][2]) {
+    if constexpr (F32) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) bf[i][t] = x[t];
+    } else {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        float y[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) y[j] = x[8 * s + j];
+        FfOps<T>::split(y, bh[i][s], bl[i][s]);
       }
+    }
   };
 
-  FfPiece<NSUB> pc(tid);
-  if (wg.b_begin < wg.b_end) {
-    pc.load(a, f, wg.b_begin, tid);
-    pc.store(stage);
-  }
-  __syncthreads();
-  for (int b = wg.b_begin; b < wg.b_end; ++b) {
+  // front half of bin b: stage-1 operands from the staged inputs, products, twiddle, transpose
+  auto front = [&](int b) {
     const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB>();
-    if (b + 1 < wg.b_end) pc.load(a, f, b + 1, tid);
-    const float inv = 16.0f * a.inv_scale[(size_t)f * a.n_sel + b];
-
     const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * kFfRow) + q2 * kFfRow + 8 * h;
+    // propagator at the lane's 8 wavenumbers (Eq. 2): phase in FP64 reduced to
+    // [-1/2, 1/2] cycle, hardware sin/cos; evanescent values (kz < 0 in the table) are
+    // replaced in one branch taken only by lanes that hold any
     float2 H[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) H[m] = z >= 0.0 ? propagator(z, kzr[m], a.zero_evanescent) : make_float2(0.f, 0.f);
+    for (int m = 0; m < 8; ++m) {
+      const double ph = z * kzr[m];
+      const float r = (float)(ph - rint(ph));
+      H[m] = make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+    }
+    if (a.ev_bin[b]) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        if (kzr[m] < 0.0) H[m] = propagator(z, kzr[m], a.zero_evanescent);
+    }
+    float bf[NSUB][16];
     v8 bh[NSUB][2], bl[NSUB][2];
 #pragma unroll
     for (int i = 0; i < NSUB; ++i) {
       const float4* g = reinterpret_cast<const float4*>(st + (i * 16 + q2) * kFfRow + 8 * h);
+      float x[16];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        float x[8];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const float4 gg = g[2 * s + k];
-          const float2 a0 = cmul(H[4 * s + 2 * k], make_float2(gg.x, gg.y));
-          const float2 a1 = cmul(H[4 * s + 2 * k + 1], make_float2(gg.z, gg.w));
-          x[4 * k] = a0.x;
-          x[4 * k + 1] = a0.y;
-          x[4 * k + 2] = a1.x;
-          x[4 * k + 3] = a1.y;
-        }
-        FfSplit<T>::split(x, bh[i][s], bl[i][s]);
+      for (int k = 0; k < 4; ++k) {
+        const float4 gg = g[k];
+        const float2 a0 = cmul(H[2 * k], make_float2(gg.x, gg.y));
+        const float2 a1 = cmul(H[2 * k + 1], make_float2(gg.z, gg.w));
+        x[4 * k] = a0.x;
+        x[4 * k + 1] = a0.y;
+        x[4 * k + 2] = a1.x;
+        x[4 * k + 3] = a1.y;
       }
+      put(i, x, bf, bh, bl);
     }
     v16f C[NSUB];
-    gemm(bh, bl, C);
-
+    gemm(bf, bh, bl, C);
 #pragma unroll
     for (int i = 0; i < NSUB; ++i)
 #pragma unroll
@@ -405,20 +319,62 @@ __global__ __launch_bounds__(512, 1) void k3ff_split(K3Args a) {
         tr[i * 2 * kFfZz + zz * kFfZz + x1 * kFfRow + q2] = cmul(make_float2(C[i][v], C[i][v + 8]), tw.t[v]);
       }
     __builtin_amdgcn_wave_barrier();
+  };
+
+  // back half of bin b: stage-3 operands from the transpose buffer, products, fold
+  auto back = [&](int b) {
+    float bf[NSUB][16];
+    v8 bh[NSUB][2], bl[NSUB][2];
 #pragma unroll
     for (int i = 0; i < NSUB; ++i) {
       const float4* y = reinterpret_cast<const float4*>(tr + i * 2 * kFfZz + zz * kFfZz + q2 * kFfRow + 8 * h);
+      float x[16];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const float4 y0 = y[2 * s], y1 = y[2 * s + 1];
-        const float x[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
-        FfSplit<T>::split(x, bh[i][s], bl[i][s]);
+      for (int k = 0; k < 4; ++k) {
+        const float4 yy = y[k];
+        x[4 * k] = yy.x;
+        x[4 * k + 1] = yy.y;
+        x[4 * k + 2] = yy.z;
+        x[4 * k + 3] = yy.w;
+      }
+      put(i, x, bf, bh, bl);
+    }
+    v16f C[NSUB];
+    gemm(bf, bh, bl, C);
+    const float inv = SCALED ? 16.0f * a.inv_scale[(size_t)f * a.n_sel + b] : 1.0f;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      float pr[NSUB], pim[NSUB];
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) {
+        pr[i] = SCALED ? C[i][v] * inv : C[i][v];
+        pim[i] = SCALED ? C[i][v + 8] * inv : C[i][v + 8];
+        accS[i][v] = fmaf(pr[i], pr[i], fmaf(pim[i], pim[i], accS[i][v]));
+      }
+      if constexpr (NSUB == 3) {
+        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
+        accC[1][v] = fmaf(pr[1], pr[2], fmaf(pim[1], pim[2], accC[1][v]));
+        accC[2][v] = fmaf(pr[2], pr[0], fmaf(pim[2], pim[0], accC[2][v]));
+      } else if constexpr (NSUB == 2) {
+        accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
       }
     }
-    gemm(bh, bl, C);
-    ff_fold<NSUB>(C, inv, accS, accC);
+  };
 
-    if (b + 1 < wg.b_end) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB>());
+  FfPiece<NSUB> pc(tid);
+  if (wg.b_begin < wg.b_end) {
+    pc.load(a, f, wg.b_begin, tid);
+    pc.store(stage);
+  }
+  __syncthreads();
+  // one extra iteration lets the lagging waves finish their last bin
+  for (int b = wg.b_begin; b <= wg.b_end; ++b) {
+    const bool has = b < wg.b_end, more = b + 1 < wg.b_end;
+    if (more) pc.load(a, f, b + 1, tid);
+    if (lag && b > wg.b_begin) back(b - 1);
+    if (has) front(b);
+    if (!lag && has) back(b);
+    if (more) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB>());
     __syncthreads();
   }
   ff_store<NSUB>(a, wg.sp, f, d0, lane, accS, accC);

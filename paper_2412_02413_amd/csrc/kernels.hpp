@@ -31,8 +31,6 @@ namespace pam {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-constexpr double kTwoPiHi = 6.283185307179586232;      // 2 pi rounded to FP64
-
 // Row pitch of the kz tables: N/2 + 1 values padded to an even count.
 __host__ __device__ constexpr int kz_row(int N) { return N / 2 + 2; }
 
@@ -47,15 +45,17 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 // evanescent one decaying as exp(2 pi z kzc).  The phase z*kz/(2 pi) (thousands
 // of cycles at depth) is formed and reduced to [-1/2, 1/2] cycle in FP64; the
 // sine and cosine of the reduced phase come from the hardware transcendental
-// unit, whose argument is in cycles (max abs error ~1.2e-7 on [-1/2, 1/2]).
+// unit, whose argument is in cycles (max abs error ~1.2e-7 on [-1/2, 1/2]).  The
+// decay exp(2 pi z kzc) = 2^(z kzc 2 pi / ln 2) comes from the hardware exp2.
+constexpr float kTwoPiOverLn2 = 9.064720283654388f;
 __device__ __forceinline__ float2 propagator(double z, double kzc, int zero_evanescent) {
+  const double ph = z * kzc;
   if (kzc >= 0.0) {
-    const double ph = z * kzc;
     const float r = (float)(ph - rint(ph));
     return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
   }
   if (zero_evanescent) return make_float2(0.f, 0.f);
-  return make_float2(expf((float)(kTwoPiHi * z * kzc)), 0.f);
+  return make_float2(__builtin_amdgcn_exp2f((float)ph * kTwoPiOverLn2), 0.f);
 }
 
 // --------------------------------------------------------------------------
@@ -114,8 +114,10 @@ __global__ __launch_bounds__(256) void k1_time_fft(K1Args a) {
 // K2: apodize, place on the lateral grid, lateral DFT, fold into slot order (or,
 // for the factored transform, reorder the unfolded spectrum so that q = N2 q1 + q2
 // is stored at q2 N1 + q1) and scale by a power of two (exact) so that the largest
-// coefficient lies in [2^11, 2^12): this keeps FP16 hi/lo splits of the products
-// normal and is a no-op on the results.  One workgroup per (bin, frame).
+// coefficient lies in [2^11, 2^12) when the operands are FP16: this keeps FP16
+// hi/lo splits of the products normal and is a no-op on the results (FP32 and BF16
+// operands have the FP32 exponent range and take scale 1).  One workgroup per
+// (bin, frame).
 // --------------------------------------------------------------------------
 struct K2Args {
   const float2* spectra;  // [F][n_sel][L]
@@ -126,6 +128,7 @@ struct K2Args {
   int32_t L, N, n_sub, n_sel;
   int32_t col0, col_step; // grid column of element l is col0 + col_step * l
   int32_t ff_n1;          // 0: folded slot order; N1 > 0: unfolded P(q)/N in [q2][q1] order, q = (N/N1) q1 + q2
+  int32_t scaled;         // 1: power-of-two scale into [2^11, 2^12) (FP16 operands); 0: scale 1
 };
 
 template <int NSUB>
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(256) void k2_lateral(K2Args a) {
   const float gmax = red[0];
   int ex = 0;
   frexpf(gmax, &ex);  // gmax = m 2^ex, m in [0.5, 1)
-  const float scale = (gmax > 0.f) ? ldexpf(1.0f, 12 - ex) : 1.0f;
+  const float scale = (a.scaled && gmax > 0.f) ? ldexpf(1.0f, 12 - ex) : 1.0f;
   float2* dst = a.coeffs + fb * a.n_sub * N;
   for (int e = threadIdx.x; e < a.n_sub * N; e += blockDim.x) {
     const float2 g = Gf[e];
@@ -229,7 +232,8 @@ struct K3Args {
   const double* kz_ff;     // [n_sel][N2][N1] signed kz / (2 pi) at q = N2 q1 + q2
   const float* ff_w32;     // [64 lanes][16] 16-point DFT matrix, FP32 operand order
   const void* ff_w16;      // [64 lanes][2 k-steps][hi 8, lo 8] 16-point DFT matrix, 16-bit operand order
-  const float2* ff_tw;     // [64 lanes][8] twiddles e^{2 pi i q2 x1 / N} / 16 of the lane's stage-1 outputs
+  const float2* ff_tw;     // [64 lanes][8] twiddles e^{2 pi i q2 x1 / N} of the lane's stage-1 outputs (/ 16 for FP16)
+  const int32_t* ev_bin;   // [n_sel] 1 if the bin has evanescent lateral wavenumbers
 };
 
 template <int NSUB>

@@ -44,6 +44,7 @@ struct Level {
   int32_t* d_ksel = nullptr;  // bin k on the level's own grid
   double* d_kz = nullptr;     // [n_sel][kz_row(N)] signed kz / (2 pi) of the selected bins
   double* d_kzff = nullptr;   // [n_sel][N2][N1] the same values at q = N2 q1 + q2 (factored kernels)
+  int32_t* d_ev = nullptr;    // [n_sel] 1 if any lateral wavenumber of the bin is evanescent
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -348,11 +349,11 @@ hipError_t launch_ff(int precision, const pam::K3Args& a, int blocks, hipStream_
   using namespace pam;
   const size_t lds = k3ff_lds<NSUB>();
   switch (precision) {
-    case PAM_PREC_SPLIT_BF16: return launch_fused(k3ff_split<__bf16, 3, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_SPLIT_FP16: return launch_fused(k3ff_split<_Float16, 3, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_BF16: return launch_fused(k3ff_split<__bf16, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_FP16: return launch_fused(k3ff_split<_Float16, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-    default: return launch_fused(k3ff_fp32<NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_SPLIT_BF16: return launch_fused(k3ff<__bf16, 3, NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_SPLIT_FP16: return launch_fused(k3ff<_Float16, 3, NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_BF16: return launch_fused(k3ff<__bf16, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_FP16: return launch_fused(k3ff<_Float16, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
+    default: return launch_fused(k3ff<float, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
   }
 }
 
@@ -538,7 +539,8 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       for (int v = 0; v < 8; ++v) {
         const int x1 = 8 * (v / 4) + 4 * h + v % 4, q2 = c % 16;
         const double th = 2.0 * kPi * (double)((q2 * x1) % 256) / 256.0;
-        ff_tw[l * 8 + v] = make_float2((float)(std::cos(th) / 16.0), (float)(std::sin(th) / 16.0));
+        const double sc = h16 ? 1.0 / 16.0 : 1.0;   // FP16 operands keep stage-1 results in range
+        ff_tw[l * 8 + v] = make_float2((float)(std::cos(th) * sc), (float)(std::sin(th) * sc));
       }
     }
   }
@@ -585,6 +587,10 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
               kzff[(size_t)b * N + q2 * 16 + q1] = kz_lv[(size_t)b * pam::kz_row(N) + qf];
             }
         if ((st = upload(p, &lv.d_kzff, kzff.data(), kzff.size())) != PAM_OK) break;
+        std::vector<int32_t> ev(lv.n_sel, 0);
+        for (int b = 0; b < lv.n_sel; ++b)
+          for (int q = 0; q < N; ++q) ev[b] |= kzff[(size_t)b * N + q] < 0.0 ? 1 : 0;
+        if ((st = upload(p, &lv.d_ev, ev.data(), ev.size())) != PAM_OK) break;
       }
       p->levels.push_back(lv);
     }
@@ -672,7 +678,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   // K2: lateral DFT + fold, one workgroup per (bin, frame)
   {
     pam::K2Args a{spectra, coeffs, scales, p->d_twx, p->d_masks, p->L, p->N, p->n_sub, lv->n_sel,
-                  p->col0, p->col_step, p->ff ? pam::kFfN1 : 0};
+                  p->col0, p->col_step, p->ff ? pam::kFfN1 : 0, is_fp16(p->precision) ? 1 : 0};
     const size_t lds = (size_t)(p->N + 3 * p->L + 2 * p->n_sub * p->N) * sizeof(float2);
     if (p->n_sub == 3)
       hipLaunchKernelGGL(pam::k2_lateral<3>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
@@ -687,7 +693,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
     const LaunchShape s = k3_shape(p, F, lv->n_sel);
     pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, p->d_basis_lane, accum,
                   p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent,
-                  lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw};
+                  lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw, lv->d_ev};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
     if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
     if (launch_k3(p->precision, p->n_sub, s, a, (int)blocks, stream) != hipSuccess || !mark(3))
