@@ -117,7 +117,10 @@ typedef struct {
 /* Where each stage's result lies inside a workspace (byte offsets), for callers
  * that check intermediate results.  Layouts (all row-major, last index fastest):
  *   spectra  complex64 [F][n_sel][L]          time-transform bins, Omega order
- *   coeffs   complex64 [F][n_sel][n_sub][N_x] folded lateral coefficients, scaled
+ *   coeffs   complex64 [F][n_sel][n_sub][N_x] lateral coefficients: at N_x = 256 the
+ *            spectrum P_i(q)/N_x stored at q2*16 + q1 for q = 16 q1 + q2 (factored
+ *            transform), otherwise folded into cos/sin slot order; scaled by a power of
+ *            two for FP16 operands (scale 1 otherwise)
  *   scales   float32   [F][n_sel]             1 / (power-of-two scale of coeffs)
  *   accum    float32   [n_split][F][n_acc][n_z][N_x] partial sums over disjoint bin
  *            ranges; channels S_1..S_nsub then C_12, C_23, C_31 (n_sub = 3) or C_12
@@ -172,6 +175,26 @@ pam_status_t pam_as_tax_events(pam_plan_t p, const float* rf, int64_t n_frames, 
                                float* image, float* nncc, float* rho_pairs,
                                void* workspace, size_t ws_bytes, void* hip_stream,
                                void* const* events);
+
+/* Bytes of the library's built-in device scratch used by pam_as_tax_noalloc (64 MiB:
+ * one frame of 128 elements x 4096 samples x 768 bins on a 512 x 256 grid needs 54 MB). */
+#define PAM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* pam_as_tax without a caller workspace and without any allocation, for callers that
+ * cannot allocate device memory (work captured into a HIP graph, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments (minus the workspace), validation
+ * and results as pam_as_tax; the intermediate results live in a device array of
+ * PAM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends.
+ *   Errors: PAM_ERR_WORKSPACE when the call needs more scratch than
+ *   PAM_NOALLOC_SCRATCH_BYTES (pam_workspace_size gives the need; split the frames
+ *   into smaller calls); otherwise as pam_as_tax.
+ *   Concurrency: every call on one GPU shares that GPU's scratch, which keeps the last
+ *   call's contents; calls that overlap on one GPU (other streams, other threads) race
+ *   and must be serialised by the caller.  No stage needs the scratch cleared: every
+ *   value a kernel reads was written earlier in the same call. */
+pam_status_t pam_as_tax_noalloc(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t,
+                                float* image, float* nncc, float* rho_pairs, void* hip_stream);
 
 /* Release the plan's device tables.  NULL-safe; no work may be in flight. */
 void pam_destroy(pam_plan_t p);

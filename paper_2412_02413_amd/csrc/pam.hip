@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -731,5 +732,56 @@ pam_status_t pam_as_tax_events(pam_plan_t p, const float* rf, int64_t n_frames, 
 }
 
 void pam_destroy(pam_plan_t p) { free_plan(p); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Entry point that allocates nothing: the workspace is a file-scope device array.
+// In host code `scratch` names a host-side stand-in, not device memory; its device
+// address on each GPU comes from hipGetSymbolAddress (taken once per device, with
+// that device current) and only that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[PAM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the caller has made it current).
+pam_status_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return PAM_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PAM_ERR_DEVICE;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return PAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pam_status_t pam_as_tax_noalloc(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
+                                float* nncc, float* rho_pairs, void* hip_stream) {
+  if (!p || n_frames < 0) return PAM_ERR_INVALID_ARG;
+  pam_workspace_layout_t W;
+  pam_status_t st = layout(p, n_frames, n_t, &W);
+  if (st != PAM_OK) return st;
+  if (W.total > (size_t)PAM_NOALLOC_SCRATCH_BYTES) return PAM_ERR_WORKSPACE;
+  if (n_frames == 0) return PAM_OK;
+  void* ws = nullptr;
+  {
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return PAM_ERR_DEVICE;
+    if ((st = scratch_address(p->device, &ws)) != PAM_OK) return st;
+  }
+  return run_as_tax(p, rf, n_frames, n_t, image, nncc, rho_pairs, ws, (size_t)PAM_NOALLOC_SCRATCH_BYTES,
+                    hip_stream, nullptr);
+}
 
 }  // extern "C"

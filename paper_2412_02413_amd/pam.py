@@ -79,6 +79,8 @@ def _lib():
         lib.pam_as_tax.restype = C.c_int
         lib.pam_as_tax_events.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp, C.POINTER(vp)]
         lib.pam_as_tax_events.restype = C.c_int
+        lib.pam_as_tax_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp]
+        lib.pam_as_tax_noalloc.restype = C.c_int
         lib.pam_destroy.argtypes = [vp]
         lib.pam_destroy.restype = None
         lib.pam_status_string.argtypes = [C.c_int]
@@ -235,6 +237,23 @@ def pam_as_tax(plan: Plan, rf, image, nncc=None, rho_pairs=None, workspace=None,
     st = _lib().pam_as_tax(C.c_void_p(plan.handle), _ptr(rf), F, n_t, _ptr(image), _ptr(nncc),
                            _ptr(rho_pairs), _ptr(workspace), ws_bytes, C.c_void_p(stream.cuda_stream))
     _check(st, "pam_as_tax")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def pam_as_tax_noalloc(plan: Plan, rf, image, nncc=None, rho_pairs=None, stream=None,
+                       n_t: Optional[int] = None) -> None:
+    """pam_as_tax on the library's built-in device scratch (no workspace, no allocation)."""
+    import torch
+    F = int(rf.shape[0])
+    n_t = int(rf.shape[-1]) if n_t is None else n_t
+    check_buffers(plan.info, rf, image, nncc, rho_pairs, None, n_t)
+    if stream is None:
+        stream = torch.cuda.current_stream(rf.device)
+    st = _lib().pam_as_tax_noalloc(C.c_void_p(plan.handle), _ptr(rf), F, n_t, _ptr(image), _ptr(nncc),
+                                   _ptr(rho_pairs), C.c_void_p(stream.cuda_stream))
+    _check(st, "pam_as_tax_noalloc")
 
 
 N_STAGE_EVENTS = 5
