@@ -6,13 +6,24 @@ resident in HBM): 128-element array, pitch 0.3 mm, 4096 samples at 40 MHz,
 emitters per frame at random positions, 20 dB channel noise (synthetic; the
 paper's recordings are not available).
 
-Prints ONE JSON line on stdout: throughput (frames/s), per-frame latency
-p50/p99 of single-frame calls, the dominant kernel's roofline figures measured
-live with HIP events on the library's stream, the error of the GPU result against
-the FP64 oracle on one frame, and the oracle itself timed on the host CPU
-(a reported baseline, not the target).  Beside the main form: the other precision
-forms of the DFT-GEMM, and the NCC-mask surrogate (committed weights) on the same
-frames, with its fallback rate and its image against plain AS-TAX's.
+Prints ONE JSON line on stdout:
+  * throughput (frames/s) and single-frame latency p50/p99 of the main form;
+  * the dominant kernel (fields: propagator + two-stage DFT-GEMM + cross-spectra)
+    against its roofline, timed live with HIP events on the library's stream:
+    `frac` counts the method's own algorithmic flops (lateral inverse FFTs,
+    propagator products, cross-spectra sums), `mfma_util` the matrix-core flops
+    the kernel executes;
+  * the other operand forms of the DFT-GEMM on the same frames;
+  * the error of every form against the FP64 oracle (max and mean over 16 frames
+    of this workload and 64 frames of the 64-element workload), computed by oracle
+    processes on the host while the GPU legs run;
+  * the mixed-record-length workload (64 frames of 2048/4096/8192 samples on one
+    8192-sample plan) per form, with its error against the oracle per length;
+  * the NCC-mask surrogate, the paper-shape context timings, host-copy-inclusive
+    throughput, and a serving leg (Poisson arrivals at 100 / 1,000 / 5,000 frames/s
+    over a fixed horizon);
+  * the oracle timed on the host CPU (all cores and one thread; a reported
+    baseline, not the target).
 Diagnostics go to stderr.
 """
 from __future__ import annotations
@@ -34,62 +45,66 @@ METRIC = "AS-TAX frames/s and p99 ms/frame (128ch, 256×512); surrogate/split vs
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0, "bf16": 2500.0, "fp16": 2500.0}
 MFMA_PASSES = {"fp32": 1, "split_bf16": 3, "split_fp16": 3, "bf16": 1, "fp16": 1}
+ACC_FRAMES_BENCH = 16       # frames of the benchmark workload checked against the oracle
+ACC_FRAMES_SMALL = 64       # frames of the 64-element workload checked against the oracle
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# ----------------------------------------------------------------------------
+# work and bytes
+# ----------------------------------------------------------------------------
+
 def executed_mfma_flops(geom, n_sel: int, n_frames: int, precision: str) -> float:
-    """Matrix-core flops one launch of the fields kernel executes: per (frame, bin) a
-    real GEMM of (2 n_sub * 32-padded depths) x N_x x N_x (folded real basis), times the
-    number of product passes of the precision mode."""
-    n_z_pad = 32 * math.ceil(geom.n_z / 32)
-    return 2.0 * (2 * geom.n_sub) * n_z_pad * geom.n_x * geom.n_x * n_sel * n_frames * MFMA_PASSES[precision]
+    """Matrix-core flops one launch of the fields kernel executes.  N_x = 256 (factored
+    transform): per (frame, bin, sub-aperture, depth) two 16-point complex DFT stages in
+    real form, 2 x 32 x 32 x 2 flops per 16 outputs each, on depths padded to 16;
+    otherwise the folded dense form, a real GEMM of (2 n_sub 32-padded depths) x N x N.
+    Times the product passes of the operand form."""
+    N, ns = geom.n_x, geom.n_sub
+    if N == 256:
+        per = ns * n_sel * 16 * math.ceil(geom.n_z / 16) * N * 256.0
+    else:
+        per = 2.0 * (2 * ns) * 32 * math.ceil(geom.n_z / 32) * N * N * n_sel
+    return per * n_frames * MFMA_PASSES[precision]
 
 
-def algorithmic_flops(geom, n_sel: int) -> float:
-    """FFT-equivalent work of one frame (5 N log2 N per complex FFT): lateral inverse FFTs,
-    propagator products, 12 FMAs of cross-spectra per pixel and bin, time and lateral FFTs."""
+def fields_algorithmic_flops(geom, n_sel: int) -> float:
+    """The method's own work in the fields step per frame (complexity terms of the paper's
+    run-time analysis, 5 N log2 N flops per complex FFT): the lateral inverse FFTs of every
+    sub-aperture, bin and depth, the propagator products, and 12 FMAs of cross-spectra
+    per pixel and bin."""
     N, nz, ns = geom.n_x, geom.n_z, geom.n_sub
     lat_ifft = ns * n_sel * nz * 5 * N * math.log2(N)
     prop = ns * n_sel * nz * N * 6
     cross = n_sel * nz * N * 24
+    return lat_ifft + prop + cross
+
+
+def algorithmic_flops(geom, n_sel: int) -> float:
+    """Whole-path algorithmic work per frame: the fields terms plus the time and lateral
+    forward FFTs."""
+    N, ns = geom.n_x, geom.n_sub
     t_fft = geom.n_elements * 5 * (geom.n_samples / 2) * math.log2(geom.n_samples / 2)
     lat_fft = ns * n_sel * 5 * N * math.log2(N)
-    return lat_ifft + prop + cross + t_fft + lat_fft
+    return fields_algorithmic_flops(geom, n_sel) + t_fft + lat_fft
 
 
-def make_frames(n: int, base_seed: int = 0) -> np.ndarray:
-    from paper_2412_02413_amd import synth
-    return np.stack([synth.cfg2_frame(base_seed + i)[0] for i in range(n)])
-
-
-def err(img, rho, ref):
-    return {"rel_l2_image": float(np.linalg.norm(img - ref["I"]) / np.linalg.norm(ref["I"])),
-            "max_abs_nncc": float(np.abs(rho - ref["rho_n"]).max()), "frames": 1}
-
-
-def cpu_baseline(rf0: np.ndarray, geom):
-    """FP64 oracle on one full cfg2 frame on the host cores."""
-    from oracle import as_tax as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    ref = O.as_tax(rf0, geom)
-    dt = time.perf_counter() - t0
-    return ref, {"value": 1.0 / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
-                 "sample": f"1 full frame of the benchmark workload (seed 0): {dt:.1f} s"}
+def algorithmic_bytes(lay, n_frames: int, n_sel: int, geom) -> float:
+    """Bytes the fields kernel must move once per launch: the lateral coefficients of every
+    (frame, bin, sub-aperture) in, the accumulated energy and cross-spectra sums out."""
+    coeffs = n_frames * n_sel * geom.n_sub * geom.n_x * 8
+    accum = lay.n_split * n_frames * lay.n_acc * geom.n_z * geom.n_x * 4
+    return float(coeffs + accum)
 
 
 def source_digest() -> str:
     """SHA-256 of the fields kernel's sources: traffic counters stay valid only for this code."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hpp", "k3_fields.hpp", "k3_fields16.hpp", "k3_fields_fused.hpp"):
+    for name in ("kernels.hpp", "k3_factored.hpp"):
         with open(os.path.join(ROOT, "paper_2412_02413_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -116,27 +131,196 @@ def recorded_traffic(precision: str):
     return vals.get(precision)
 
 
-def algorithmic_bytes(lay, n_frames: int, n_sel: int, geom) -> float:
-    """Bytes the fields kernel must move once per launch: the lateral coefficients of every
-    (frame, bin, sub-aperture) in, the accumulated energy and cross-spectra sums out."""
-    coeffs = n_frames * n_sel * geom.n_sub * geom.n_x * 8
-    accum = lay.n_split * n_frames * lay.n_acc * geom.n_z * geom.n_x * 4
-    return float(coeffs + accum)
+# ----------------------------------------------------------------------------
+# the oracle on the host (separate processes, started before the GPU is touched)
+# ----------------------------------------------------------------------------
+
+def _oracle_job(job: str, threads: int, conn) -> None:
+    """FP64 oracle results for the accuracy check: I and rho_n per frame, plus timing."""
+    from threadpoolctl import threadpool_limits
+    from oracle import as_tax as O
+    from paper_2412_02413_amd import synth
+    out = {"job": job, "threads": threads, "frames": {}, "seconds": []}
+    with threadpool_limits(threads):
+        if job == "bench":
+            g = synth.cfg2_geometry()
+            for s in range(ACC_FRAMES_BENCH):
+                rf = synth.cfg2_frame(s)[0]
+                t0 = time.perf_counter()
+                r = O.as_tax(rf, g)
+                out["seconds"].append(time.perf_counter() - t0)
+                out["frames"][s] = (r["I"], r["rho_n"])
+        else:
+            g = synth.cfg1_geometry()
+            for s in range(ACC_FRAMES_SMALL):
+                rf = synth.cfg1_frame(s)
+                t0 = time.perf_counter()
+                r = O.as_tax(rf, g)
+                out["seconds"].append(time.perf_counter() - t0)
+                out["frames"][s] = (r["I"], r["rho_n"])
+            g3 = synth.cfg3_geometry()
+            seen = set()
+            out["mixed"] = {}
+            for s in range(64):
+                rf = synth.cfg3_frame(s)
+                n_t = rf.shape[-1]
+                if n_t in seen:
+                    continue
+                seen.add(n_t)
+                r = O.as_tax(rf, g3.replace(n_samples=n_t))
+                out["mixed"][n_t] = (s, r["I"], r["rho_n"])
+    conn.send(out)
+    conn.close()
 
 
-def copy_calibration(dev, mib: int = 1024, reps: int = 3):
-    """Plain device copies of a known size (outside any timed region): the per-dispatch
-    FETCH_SIZE / WRITE_SIZE counters of these copies scale the fields kernel's counters."""
-    import torch
-    n = mib * (1 << 20) // 4
-    src = torch.ones(n, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    for _ in range(reps):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    log(f"copy calibration: {reps} device copies of {mib} MiB")
-    del src, dst
+def start_oracles(threads_each: int):
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    procs = []
+    for job in ("bench", "small"):
+        recv, send = ctx.Pipe(duplex=False)
+        p = ctx.Process(target=_oracle_job, args=(job, threads_each, send), daemon=True)
+        p.start()
+        procs.append((job, p, recv))
+    return procs
+
+
+def join_oracles(procs, timeout_s: float = 600.0):
+    res = {}
+    for job, p, recv in procs:
+        if recv.poll(timeout_s):
+            res[job] = recv.recv()
+        p.join(30)
+    return res
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(oracle_res: dict, threads_all: int) -> dict:
+    """The oracle as it stands on the host cores.  All-core figures come from the accuracy
+    runs (16 benchmark frames, 64 small frames, one oracle process each); the one-thread
+    figure times the oracle on one benchmark frame restricted to every 16th bin (48 of
+    768 bins: the work is linear in the bin count) and scales it to the whole frame; the
+    paper-shape frame (690 bins, 300 x 256) runs once on all cores."""
+    from threadpoolctl import threadpool_limits
+    from oracle import as_tax as O
+    from paper_2412_02413_amd import synth
+    out = {"kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+    b = oracle_res.get("bench")
+    if b and b["seconds"]:
+        sec = float(np.mean(b["seconds"]))
+        out.update({"value": round(1.0 / sec, 4), "unit": "frames/s", "cores": b["threads"],
+                    "sample": f"{len(b['seconds'])} frames of the benchmark workload, {b['threads']} threads "
+                              f"(BLAS), {sec:.2f} s per frame"})
+    s = oracle_res.get("small")
+    if s and s["seconds"]:
+        sec = float(np.mean(s["seconds"]))
+        out["small_workload"] = {"frames_per_s": round(1.0 / sec, 3), "threads": s["threads"],
+                                 "sample": f"{len(s['seconds'])} frames of the 64-element workload"}
+    # one thread on a bin subset of one benchmark frame
+    g = synth.cfg2_geometry()
+    ks = O.bins(g.fs_hz, g.n_samples, g.bands_hz)
+    sub = ks[::16]
+    bands = [(k * g.fs_hz / g.n_samples, k * g.fs_hz / g.n_samples) for k in sub]
+    rf = synth.cfg2_frame(0)[0]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.as_tax(rf, g.replace(bands_hz=bands))
+        dt = time.perf_counter() - t0
+    per_frame = dt * len(ks) / len(sub)
+    out["one_thread"] = {"value": round(1.0 / per_frame, 5), "unit": "frames/s", "cores": 1,
+                         "sample": f"one benchmark frame on {len(sub)} of {len(ks)} bins: {dt:.2f} s, "
+                                   f"scaled to {per_frame:.1f} s per frame"}
+    # paper shape, all cores
+    gp = synth.paper_geometry(690)
+    rfp = synth.paper_frame(0, 690)
+    with threadpool_limits(threads_all):
+        t0 = time.perf_counter()
+        O.as_tax(rfp, gp)
+        dt = time.perf_counter() - t0
+    out["paper_shape_690_bins"] = {"seconds_per_frame": round(dt, 3), "threads": threads_all,
+                                   "paper_context": "Xeon 3 GHz, one thread, Matlab: 8.4 s (Table III)"}
+    return out
+
+
+# ----------------------------------------------------------------------------
+# GPU legs
+# ----------------------------------------------------------------------------
+
+def errors_vs_oracle(images, nncc, refs) -> dict:
+    """Relative L2 of the image and max |d rho_n| over all pixels, max and mean over frames."""
+    e_i, e_r = [], []
+    for f, (I, rho) in refs.items():
+        e_i.append(float(np.linalg.norm(images[f] - I) / np.linalg.norm(I)))
+        e_r.append(float(np.abs(nncc[f] - rho).max()))
+    if not e_i:
+        return None
+    return {"rel_l2_image_max": max(e_i), "rel_l2_image_mean": float(np.mean(e_i)),
+            "max_abs_nncc_max": max(e_r), "max_abs_nncc_mean": float(np.mean(e_r)), "frames": len(e_i)}
+
+
+def run_frames(pam, torch, geom, rf_np, precision, dev):
+    """One launch over host frames (all of one record length); images and NNCC back on the host."""
+    plan = pam.pam_plan(geom, 0, precision)
+    try:
+        x = torch.from_numpy(np.ascontiguousarray(rf_np, np.float32)).to(dev)
+        out = pam.reconstruct(plan, x, want_nncc=True)
+        torch.cuda.synchronize()
+        return out["image"].cpu().numpy().astype(np.float64), out["nncc"].cpu().numpy().astype(np.float64)
+    finally:
+        pam.pam_destroy(plan)
+
+
+def mixed_lengths(pam, torch, precisions, steps, dev):
+    """64 frames of the 64-element array with record lengths drawn from 2048/4096/8192 on one
+    8192-sample plan: one launch per record length on one stream (the bins of a record are
+    every 2nd / 4th bin of the plan's), timed over all 64 frames."""
+    from paper_2412_02413_amd import synth
+    g = synth.cfg3_geometry()
+    frames = [synth.cfg3_frame(s) for s in range(64)]
+    lengths = sorted({fr.shape[-1] for fr in frames})
+    groups = {n: [i for i, fr in enumerate(frames) if fr.shape[-1] == n] for n in lengths}
+    dev_rf = {n: torch.from_numpy(np.stack([frames[i] for i in idx])).to(dev) for n, idx in groups.items()}
+    out = {"frames": 64, "record_lengths": {str(n): len(idx) for n, idx in groups.items()}}
+    firsts = {}
+    for prec in precisions:
+        plan = pam.pam_plan(g, 0, prec)
+        try:
+            stream = torch.cuda.current_stream(dev)
+            bufs = {}
+            for n, x in dev_rf.items():
+                F = x.shape[0]
+                bufs[n] = (torch.empty((F, g.n_z, g.n_x), device=dev), torch.empty((F, g.n_z, g.n_x), device=dev),
+                           pam.alloc_workspace(plan, F, n, dev))
+
+            def step():
+                for n, x in dev_rf.items():
+                    img, nn, ws = bufs[n]
+                    pam.pam_as_tax(plan, x, img, nn, None, ws, stream, n)
+
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            out[prec] = {"frames_per_s": round(64 * steps / wall, 2), "ms_per_64_frames": round(1e3 * wall / steps, 3)}
+            firsts[prec] = {n: (bufs[n][0][0].cpu().numpy().astype(np.float64),
+                                bufs[n][1][0].cpu().numpy().astype(np.float64)) for n in groups}
+        finally:
+            pam.pam_destroy(plan)
+    return out, firsts, groups
 
 
 def surrogate_entry(geom, rf, plain_images, fps_plain, precision, steps, warmup, path):
@@ -170,6 +354,7 @@ def surrogate_entry(geom, rf, plain_images, fps_plain, precision, steps, warmup,
             "fallback_rate": round(fb / (F * steps), 4),
             "image_rel_l2_vs_plain_mean": round(float(rel.mean()), 4),
             "image_rel_l2_vs_plain_p95": round(float(rel.quantile(0.95)), 4),
+            "image_rel_l2_vs_plain_max": round(float(rel.max()), 4),
             "abs_d_isnr_db_mean": round(float((isnr_s - isnr_p).abs().mean()), 3),
             "network": f"U-Net {net.levels} levels, {net.base} base channels, BF16 operands, FP32 accumulation",
             "weights": os.path.relpath(path, ROOT)}
@@ -275,6 +460,54 @@ def pcie_inclusive(geom, rf_host, precision, steps, dev):
             "steps": steps, "copies": "RF host->device and image device->host per launch, pinned host memory"}
 
 
+def serving_entry(precision: str, horizon_s: float, loads=(100.0, 1000.0, 5000.0)) -> dict:
+    """Continuous-batching server under Poisson arrivals: for each offered load, requests
+    arrive over `horizon_s` seconds; batches are admitted until horizon + 2 s, after which
+    the queued remainder counts as unserved and only batches in flight drain.  The mix is
+    64/128/256-element arrays (128x256 / 256x512 / 512x1024 grids) at 20/40 MHz with records
+    of 1024-16384 samples."""
+    from paper_2412_02413_amd import serving as SV
+    t = time.perf_counter()
+    pool = SV.make_pool()
+    log(f"serving pool of {len(pool)} frames in {time.perf_counter() - t:.1f} s")
+    srv = SV.Server(max_batch=16, n_streams=4, precision=precision, hbm_budget=32 << 30)
+    out = {"precision": precision, "horizon_s": horizon_s, "admission_deadline_s": horizon_s + 2.0,
+           "max_batch": 16, "streams": 4, "hbm_budget_gib": 32,
+           "mix": "64/128/256 elements x 20/40 MHz x 1024-16384 samples", "loads": []}
+    try:
+        srv.run(SV.poisson_requests(pool, 1e6, len(pool), seed=99), realtime=False)     # plans + warm-up
+        for rate in loads:
+            srv.batch_sizes.clear()
+            srv.stats.clear()
+            reqs = SV.poisson_requests(pool, rate, max(1, int(rate * horizon_s)), seed=int(rate))
+            srv.run(reqs, deadline_s=horizon_s + 2.0)
+            s = SV.summarize(reqs, rate)
+            s["mean_batch"] = round(float(np.mean(srv.batch_sizes)), 2) if srv.batch_sizes else 0
+            s["admission_stalls"] = srv.stats["admission_stalls"]
+            out["loads"].append(s)
+            log(f"serving: {s}")
+    finally:
+        srv.close()
+    return out
+
+
+def copy_calibration(dev, mib: int = 1024, reps: int = 3):
+    """Plain device copies of a known size (outside any timed region): the per-dispatch
+    FETCH_SIZE / WRITE_SIZE counters of these copies scale the fields kernel's counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {reps} device copies of {mib} MiB")
+    del src, dst
+
+
+# ----------------------------------------------------------------------------
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,7 +516,9 @@ def main():
     ap.add_argument("--frames", type=int, default=64, help="frames per launch")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--latency-calls", type=int, default=1000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (accuracy check and CPU baseline)")
+    ap.add_argument("--oracle-threads", type=int, default=7, help="BLAS threads of each of the two oracle processes")
     ap.add_argument("--variants", default="split_bf16,split_fp16,bf16,fp16",
                     help="other precision forms measured beside the main one (comma list, '' for none)")
     ap.add_argument("--surrogate", default=os.path.join(ROOT, "paper_2412_02413_amd", "weights",
@@ -291,6 +526,9 @@ def main():
                     help="surrogate weights measured beside plain AS-TAX ('' for none)")
     ap.add_argument("--no-paper-shape", dest="paper_shape", action="store_false",
                     help="skip the paper-shape (690 / 128 bins, 300 x 256) context timing")
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false", help="skip the mixed-record-length leg")
+    ap.add_argument("--serving-horizon", type=float, default=1.5,
+                    help="seconds of Poisson arrivals per offered load (0 skips the serving leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with plain device copies of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -298,6 +536,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); frames are independent, "
               "so a multi-GPU run would shard frames across devices with no exchange.", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle processes start before anything touches the GPU
+    procs = start_oracles(args.oracle_threads) if not args.no_cpu_baseline else []
 
     import torch
     from paper_2412_02413_amd import pam, synth
@@ -307,16 +548,17 @@ def main():
     geom = synth.cfg2_geometry()
     F = args.frames
     t0 = time.perf_counter()
-    rf_host = make_frames(F)
+    rf_host = np.stack([synth.cfg2_frame(i)[0] for i in range(F)])
     log(f"generated {F} frames in {time.perf_counter() - t0:.1f} s")
 
     rf = torch.from_numpy(rf_host).to(dev)
     stream = torch.cuda.current_stream(dev)
     ev = pam.HipEvents()
+    n_acc = min(ACC_FRAMES_BENCH, F)
 
     def measure(precision: str, latency_calls: int):
-        """Throughput over `steps` 64-frame launches, stage times from HIP events on the
-        library's stream, optional single-frame latency; returns a dict and frame 0's output."""
+        """Throughput over `steps` launches, stage times from HIP events on the library's
+        stream, optional single-frame latency; returns a dict with the first frames' outputs."""
         plan = pam.pam_plan(geom, 0, precision)
         image = torch.empty((F, geom.n_z, geom.n_x), device=dev)
         nncc = torch.empty_like(image)
@@ -354,48 +596,58 @@ def main():
         pam.pam_destroy(plan)
         res = {"precision": precision, "ms_per_step": 1e3 * wall / args.steps,
                "frames_per_s": F * args.steps / wall, "stage_ms": stage_ms, "n_sel": n_sel,
-               "lat_gpu": lat_gpu, "lat_wall": lat_wall, "layout": lay, "images": image}
+               "lat_gpu": lat_gpu, "lat_wall": lat_wall, "layout": lay, "images": image,
+               "acc_images": image[:n_acc].cpu().numpy().astype(np.float64),
+               "acc_nncc": nncc[:n_acc].cpu().numpy().astype(np.float64)}
         log(f"{precision}: {res['ms_per_step']:.2f} ms/step, {res['frames_per_s']:.1f} frames/s, "
             f"stages {stage_ms}")
-        return res, image[0].cpu().numpy().astype(np.float64), nncc[0].cpu().numpy().astype(np.float64)
+        return res
 
-    main_res, img0, rho0 = measure(args.precision, args.latency_calls)
+    def fields_roofline(r, precision):
+        k3_ms = r["stage_ms"]["fields"]
+        alg = fields_algorithmic_flops(geom, r["n_sel"]) * F
+        exe = executed_mfma_flops(geom, r["n_sel"], F, precision)
+        peak = MFMA_PEAK_TFLOPS[precision]
+        ach = alg / (k3_ms * 1e-3) / 1e12
+        util = exe / (k3_ms * 1e-3) / 1e12
+        return {"kernel": "fields (propagator + two-stage DFT-GEMM + cross-spectra)", "bound": "mfma",
+                "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                "ms": round(k3_ms, 3), "algorithmic_flops_per_launch": alg,
+                "mfma_executed_flops_per_launch": exe, "mfma_tflops": round(util, 2),
+                "mfma_util": round(util / peak, 4)}
+
+    main_res = measure(args.precision, args.latency_calls)
     fps, ms_per_step, stage_ms, n_sel = (main_res["frames_per_s"], main_res["ms_per_step"],
                                          main_res["stage_ms"], main_res["n_sel"])
     lat_gpu, lat_wall = main_res["lat_gpu"], main_res["lat_wall"]
     if lat_gpu:
         log(f"latency: p50 {np.percentile(lat_gpu, 50):.3f} ms p99 {np.percentile(lat_gpu, 99):.3f} ms (GPU)")
+    roof = fields_roofline(main_res, args.precision)
+    roof["traffic"] = recorded_traffic(args.precision)
+    roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(main_res["layout"], F, n_sel, geom)
+    roof["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
-    # roofline of the dominant kernel (fields: propagate + DFT-GEMM + cross-spectra)
-    k3_ms = stage_ms["fields"]
-    flops = executed_mfma_flops(geom, n_sel, F, args.precision)
-    achieved = flops / (k3_ms * 1e-3) / 1e12
-    peak = MFMA_PEAK_TFLOPS[args.precision]
-    alg = algorithmic_flops(geom, n_sel)
-    traffic = recorded_traffic(args.precision)
-    alg_bytes = algorithmic_bytes(main_res["layout"], F, n_sel, geom)
-
-    # accuracy on frame 0 against the oracle, and the oracle's own speed on the host
-    out = {}
-    ref = None
-    if not args.no_cpu_baseline:
-        ref, cpu = cpu_baseline(rf_host[0], geom)
-        out["error_vs_oracle"] = err(img0, rho0, ref)
-        log(f"oracle: {cpu['sample']}; error {out['error_vs_oracle']}")
-    else:
-        cpu = None
-
-    variants = {}
-    for prec in [v for v in args.variants.split(",") if v and v != args.precision]:
-        r, im, rh = measure(prec, 0)
-        del r["images"]
-        k3v = r["stage_ms"]["fields"]
-        fl = executed_mfma_flops(geom, r["n_sel"], F, prec)
+    precisions = [args.precision] + [v for v in args.variants.split(",") if v and v != args.precision]
+    variants, acc_out = {}, {args.precision: (main_res["acc_images"], main_res["acc_nncc"])}
+    for prec in precisions[1:]:
+        r = measure(prec, 0)
+        acc_out[prec] = (r["acc_images"], r["acc_nncc"])
+        rv = fields_roofline(r, prec)
         variants[prec] = {"frames_per_s": round(r["frames_per_s"], 2), "ms_per_step": round(r["ms_per_step"], 3),
-                          "speedup_vs_plain": round(r["frames_per_s"] / fps, 3),
-                          "fields_ms": round(k3v, 3),
-                          "mfma_tflops": round(fl / (k3v * 1e-3) / 1e12, 2), "mfma_peak": MFMA_PEAK_TFLOPS[prec],
-                          "error_vs_oracle": err(im, rh, ref) if ref is not None else None}
+                          "speedup_vs_plain": round(r["frames_per_s"] / fps, 3), "fields": rv}
+        del r
+
+    # the 64-element workload on the GPU (accuracy against the oracle)
+    g1 = synth.cfg1_geometry()
+    rf1 = np.stack([synth.cfg1_frame(s) for s in range(ACC_FRAMES_SMALL)])
+    small_out = {p: run_frames(pam, torch, g1, rf1, p, dev) for p in precisions}
+
+    mixed = None
+    if args.mixed:
+        mixed, mixed_first, mixed_groups = mixed_lengths(pam, torch, [p for p in precisions if p in
+                                                                      ("fp32", "split_bf16", "split_fp16")],
+                                                         max(3, args.steps // 4), dev)
+        log(f"mixed record lengths: {mixed}")
 
     sur = None
     if args.surrogate:
@@ -404,7 +656,6 @@ def main():
                                   args.surrogate)
             log(f"surrogate: {sur}")
             if args.precision != "split_bf16":
-                # the same network on a split-BF16 full-aperture propagation (fallback in split BF16)
                 sur["with_split_bf16_propagation"] = surrogate_entry(
                     geom, rf, main_res["images"], fps, "split_bf16", args.steps, args.warmup, args.surrogate)
                 log(f"surrogate, split BF16 propagation: {sur['with_split_bf16_propagation']}")
@@ -416,8 +667,39 @@ def main():
     pshape = paper_shape([args.precision, "split_bf16"], 5, dev) if args.paper_shape else None
     if pshape:
         log(f"paper shape: {pshape}")
+    serving = serving_entry(args.precision, args.serving_horizon) if args.serving_horizon > 0 else None
     if args.copy_calibration:
         copy_calibration(dev)
+    ev.close()
+
+    # accuracy against the oracle, then the oracle's own speed (nothing else running)
+    accuracy, cpu = None, None
+    if procs:
+        t0 = time.perf_counter()
+        ores = join_oracles(procs)
+        log(f"oracle results after a further {time.perf_counter() - t0:.1f} s")
+        accuracy = {}
+        for prec in precisions:
+            ent = {}
+            if "bench" in ores:
+                ent["benchmark_workload"] = errors_vs_oracle(acc_out[prec][0], acc_out[prec][1],
+                                                             ores["bench"]["frames"])
+            if "small" in ores:
+                ent["small_workload"] = errors_vs_oracle(small_out[prec][0], small_out[prec][1],
+                                                         ores["small"]["frames"])
+                if mixed is not None and prec in mixed_first:
+                    per = {}
+                    for n_t, (s, I, rho) in ores["small"]["mixed"].items():
+                        k = mixed_groups[n_t].index(s)
+                        assert k == 0
+                        img, rn = mixed_first[prec][n_t]
+                        per[str(n_t)] = {"rel_l2_image": float(np.linalg.norm(img - I) / np.linalg.norm(I)),
+                                         "max_abs_nncc": float(np.abs(rn - rho).max()), "seed": s}
+                    ent["mixed_lengths_first_frame_per_length"] = per
+            accuracy[prec] = ent
+        log(f"accuracy: {json.dumps(accuracy)}")
+        cpu = cpu_baseline(ores, 2 * args.oracle_threads)
+        log(f"cpu baseline: {cpu}")
 
     rec = {
         "metric": METRIC,
@@ -441,21 +723,18 @@ def main():
                                   "calls": len(lat_gpu), "frames_per_call": 1} if lat_gpu else None),
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_rooflines": stages_roof,
-        "roofline": {"kernel": "fields (propagate + DFT-GEMM + cross-spectra)", "bound": "mfma",
-                     "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "flops_per_launch": flops, "algorithmic_bytes_per_launch": alg_bytes,
-                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
-        "algorithmic_gflop_per_frame": round(alg / 1e9, 3),
-        "algorithmic_tflops": round(alg * fps / 1e12, 3),
+        "roofline": roof,
+        "algorithmic_gflop_per_frame": round(algorithmic_flops(geom, n_sel) / 1e9, 3),
+        "algorithmic_tflops": round(algorithmic_flops(geom, n_sel) * fps / 1e12, 3),
+        "error_vs_oracle": accuracy,
         "cpu_baseline": cpu,
         "variants": variants,
+        "mixed_record_lengths": mixed,
         "surrogate": sur,
         "pcie_inclusive": pcie,
         "paper_shape": pshape,
+        "serving": serving,
     }
-    rec.update(out)
-    ev.close()
     print(json.dumps(rec), flush=True)
 
 

@@ -176,6 +176,20 @@ pam_status_t pam_as_tax_events(pam_plan_t p, const float* rf, int64_t n_frames, 
                                void* workspace, size_t ws_bytes, void* hip_stream,
                                void* const* events);
 
+/* The comparison beamformer of the paper's appendix on the same plan, inputs and
+ * outputs: frequency-domain delay-and-sum (FD-TEA) fields
+ *   p_i(r, w) = sum_l a_i[l] F_t{s_l}(w) exp(+i w tau_l(r)),  tau_l(r) = |r - r_l| / c
+ * (Appendix "PAM with DAX and TAX", the frequency-domain form of Eq. 6 with unit
+ * distance weights; r_l the element positions on z = 0, r the plan's image grid),
+ * followed by the same cross-spectra sums, NCC, TAX weight (n_sub = 3; DAX for 2,
+ * plain FD-TEA for 1), NNCC and image as pam_as_tax (Eq. 4, Eq. 10, Eq. 11).
+ * Same arguments, layouts, workspace size, validation and errors as pam_as_tax; the
+ * plan's lateral transform tables and precision are not used (FP32 arithmetic, FP64
+ * travel-time phases). */
+pam_status_t pam_fd_tea_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t,
+                            float* image, float* nncc, float* rho_pairs,
+                            void* workspace, size_t ws_bytes, void* hip_stream);
+
 /* Bytes of the library's built-in device scratch used by pam_as_tax_noalloc (64 MiB:
  * one frame of 128 elements x 4096 samples x 768 bins on a 512 x 256 grid needs 54 MB). */
 #define PAM_NOALLOC_SCRATCH_BYTES (64u << 20)

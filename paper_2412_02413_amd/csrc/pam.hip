@@ -16,6 +16,7 @@
 #include "k3_fields16.hpp"
 #include "k3_fields_fused.hpp"
 #include "k3_factored.hpp"
+#include "k3_tea.hpp"
 
 namespace {
 
@@ -108,6 +109,11 @@ struct pam_plan_s {
   float* d_ff_w32 = nullptr;   // [64][16] 16-point DFT matrix in FP32 operand order
   uint16_t* d_ff_w16 = nullptr;  // [64][2][16] the same in 16-bit operand order, hi then lo per k-step
   float2* d_ff_tw = nullptr;   // [64][8] twiddles / 16 in stage-1 output order
+  // frequency-domain delay-and-sum (pam_fd_tea_tax)
+  double fs = 0, c = 0;        // sampling rate, sound speed
+  double dx = 0, x_first = 0;  // lateral grid spacing and coordinate of column 0
+  double xl_first = 0, pitch = 0;  // coordinate of element 0 and element pitch
+  int32_t* d_subs = nullptr;   // [L] bit i set if sub-aperture i holds element l
   std::vector<void*> allocs;
 };
 
@@ -434,6 +440,16 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     p->col_step = N / L;
     dx = g->pitch_m / p->col_step;
   }
+  // element and pixel coordinates (array centre at x = 0)
+  {
+    const double centre = p->col0 + p->col_step * (L - 1) / 2.0;
+    p->fs = g->fs_hz;
+    p->c = g->c_mps;
+    p->dx = dx;
+    p->x_first = -centre * dx;
+    p->xl_first = (p->col0 - centre) * dx;
+    p->pitch = p->col_step * dx;
+  }
   // apodization masks: explicit or Pattern-m (a_i[l] = 1 iff floor(l/m) mod n == i)
   std::vector<float> masks((size_t)p->n_sub * L, 0.f);
   const int m = g->pattern_m > 0 ? g->pattern_m : 16;
@@ -560,6 +576,13 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     if ((st = upload(p, &p->d_tw, tw.data(), tw.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_twx, twx.data(), twx.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_masks, masks.data(), masks.size())) != PAM_OK) break;
+    {
+      std::vector<int32_t> subs(L, 0);
+      for (int i = 0; i < p->n_sub; ++i)
+        for (int l = 0; l < L; ++l)
+          if (masks[(size_t)i * L + l] != 0.f) subs[l] |= 1 << i;
+      if ((st = upload(p, &p->d_subs, subs.data(), subs.size())) != PAM_OK) break;
+    }
     if ((st = upload(p, &p->d_basis, basis.data(), basis.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_basis_lane, basis_lane.data(), basis_lane.size())) != PAM_OK) break;
     // bin subsets for records of n_t / 2^j samples
@@ -640,9 +663,11 @@ pam_status_t pam_workspace_size(pam_plan_t p, int64_t n_frames, int32_t n_t, siz
 
 namespace {
 
+// method 0: angular spectrum (K1, K2, K3 fields, K4); method 1: frequency-domain
+// delay-and-sum (K1, K3 TEA fields, K4; no lateral transform)
 pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
                         float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream,
-                        void* const* events) {
+                        void* const* events, int method = 0) {
   if (!p || n_frames < 0) return PAM_ERR_INVALID_ARG;
   if (n_frames > 65535) return PAM_ERR_UNSUPPORTED;
   pam_workspace_layout_t W;
@@ -677,7 +702,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
     if (hipGetLastError() != hipSuccess || !mark(1)) return PAM_ERR_DEVICE;
   }
   // K2: lateral DFT + fold, one workgroup per (bin, frame)
-  {
+  if (method == 0) {
     pam::K2Args a{spectra, coeffs, scales, p->d_twx, p->d_masks, p->L, p->N, p->n_sub, lv->n_sel,
                   p->col0, p->col_step, p->ff ? pam::kFfN1 : 0, is_fp16(p->precision) ? 1 : 0};
     const size_t lds = (size_t)(p->N + 3 * p->L + 2 * p->n_sub * p->N) * sizeof(float2);
@@ -688,9 +713,29 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
     else
       hipLaunchKernelGGL(pam::k2_lateral<1>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
     if (hipGetLastError() != hipSuccess || !mark(2)) return PAM_ERR_DEVICE;
+  } else if (!mark(2)) {
+    return PAM_ERR_DEVICE;
+  }
+  // K3 (frequency-domain delay-and-sum): per-pixel fields and cross-spectra
+  if (method == 1) {
+    const LaunchShape s = k3_shape(p, F, lv->n_sel);
+    const int npix = p->n_z * p->N;
+    pam::TeaArgs a{spectra, lv->d_ksel, p->d_subs, p->d_z, accum, p->x_first, p->dx, p->xl_first, p->pitch,
+                   p->fs / ((double)n_t * p->c), p->L, p->N, p->n_z, lv->n_sel, F, s.n_split, s.bins_per_split,
+                   (npix + pam::TEA_THREADS - 1) / pam::TEA_THREADS};
+    const long long blocks = (long long)F * a.n_ptile * s.n_split;
+    if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
+    const size_t lds = (size_t)pam::TEA_BC * p->L * sizeof(float2);
+    if (p->n_sub == 3)
+      hipLaunchKernelGGL(pam::k3_tea<3>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
+    else if (p->n_sub == 2)
+      hipLaunchKernelGGL(pam::k3_tea<2>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
+    else
+      hipLaunchKernelGGL(pam::k3_tea<1>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
+    if (hipGetLastError() != hipSuccess || !mark(3)) return PAM_ERR_DEVICE;
   }
   // K3: fused propagate / inverse lateral transform / cross-spectra
-  {
+  if (method == 0) {
     const LaunchShape s = k3_shape(p, F, lv->n_sel);
     pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, p->d_basis_lane, accum,
                   p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent,
@@ -729,6 +774,11 @@ pam_status_t pam_as_tax_events(pam_plan_t p, const float* rf, int64_t n_frames, 
   for (int i = 0; i < PAM_N_STAGE_EVENTS; ++i)
     if (!events[i]) return PAM_ERR_INVALID_ARG;
   return run_as_tax(p, rf, n_frames, n_t, image, nncc, rho_pairs, workspace, ws_bytes, hip_stream, events);
+}
+
+pam_status_t pam_fd_tea_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
+                            float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream) {
+  return run_as_tax(p, rf, n_frames, n_t, image, nncc, rho_pairs, workspace, ws_bytes, hip_stream, nullptr, 1);
 }
 
 void pam_destroy(pam_plan_t p) { free_plan(p); }

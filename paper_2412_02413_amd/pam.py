@@ -79,6 +79,8 @@ def _lib():
         lib.pam_as_tax.restype = C.c_int
         lib.pam_as_tax_events.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp, C.POINTER(vp)]
         lib.pam_as_tax_events.restype = C.c_int
+        lib.pam_fd_tea_tax.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]
+        lib.pam_fd_tea_tax.restype = C.c_int
         lib.pam_as_tax_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp]
         lib.pam_as_tax_noalloc.restype = C.c_int
         lib.pam_destroy.argtypes = [vp]
@@ -237,6 +239,21 @@ def pam_as_tax(plan: Plan, rf, image, nncc=None, rho_pairs=None, workspace=None,
     st = _lib().pam_as_tax(C.c_void_p(plan.handle), _ptr(rf), F, n_t, _ptr(image), _ptr(nncc),
                            _ptr(rho_pairs), _ptr(workspace), ws_bytes, C.c_void_p(stream.cuda_stream))
     _check(st, "pam_as_tax")
+
+
+def pam_fd_tea_tax(plan: Plan, rf, image, nncc=None, rho_pairs=None, workspace=None, stream=None,
+                   n_t: Optional[int] = None) -> None:
+    """Frequency-domain delay-and-sum with the same weighting (FD-TEA-TAX) on the same plan."""
+    import torch
+    F = int(rf.shape[0])
+    n_t = int(rf.shape[-1]) if n_t is None else n_t
+    check_buffers(plan.info, rf, image, nncc, rho_pairs, workspace, n_t)
+    if stream is None:
+        stream = torch.cuda.current_stream(rf.device)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    st = _lib().pam_fd_tea_tax(C.c_void_p(plan.handle), _ptr(rf), F, n_t, _ptr(image), _ptr(nncc),
+                               _ptr(rho_pairs), _ptr(workspace), ws_bytes, C.c_void_p(stream.cuda_stream))
+    _check(st, "pam_fd_tea_tax")
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20

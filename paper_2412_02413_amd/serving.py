@@ -181,8 +181,12 @@ class Server:
             self.torch.cuda.synchronize(self.device)
             self._poll(time.perf_counter())
 
-    def run(self, requests: List[Request], realtime: bool = True) -> List[Request]:
-        """Serve requests whose t_arrival are offsets (s) from now; returns them with latencies."""
+    def run(self, requests: List[Request], realtime: bool = True,
+            deadline_s: Optional[float] = None) -> List[Request]:
+        """Serve requests whose t_arrival are offsets (s) from now; returns them with latencies.
+
+        With a deadline, no batch is admitted after deadline_s: requests still queued or not
+        yet arrived are marked "unserved" and only the batches in flight are drained."""
         order = sorted(requests, key=lambda r: r.t_arrival)
         for r in order:
             self.plan(r.key)          # plans exist before the clock starts (pre-run)
@@ -190,6 +194,17 @@ class Server:
         t0 = time.perf_counter()
         while pending or self.inflight or any(self.queues.values()):
             now = time.perf_counter() - t0
+            if deadline_s is not None and now > deadline_s:
+                for r in list(pending) + [r for q in self.queues.values() for r in q]:
+                    r.status = "unserved"
+                    self.stats["unserved"] += 1
+                pending.clear()
+                for q in self.queues.values():
+                    q.clear()
+                while self.inflight:
+                    self.torch.cuda.synchronize(self.device)
+                    self._poll(time.perf_counter() - t0)
+                break
             while pending and (pending[0].t_arrival <= now or not realtime):
                 self.submit(pending.popleft())
             polled = self._poll(now)
@@ -243,6 +258,7 @@ def summarize(reqs: List[Request], rate_hz: float) -> dict:
     span = (max(r.t_done for r in done) - min(r.t_arrival for r in reqs)) if done else 0.0
     return {"offered_fps": rate_hz, "requests": len(reqs), "completed": len(done),
             "rejected": sum(r.status == "rejected" for r in reqs),
+            "unserved": sum(r.status == "unserved" for r in reqs),
             "completed_fps": round(len(done) / span, 2) if span > 0 else None,
             "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "max_ms": round(float(lat.max()), 3)}

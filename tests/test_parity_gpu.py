@@ -329,3 +329,23 @@ def test_factored_transform_forms(pam, torch_cuda, precision, n_sub):
     tol_i, tol_rho = {"fp32": (TOL_I, TOL_RHO), "bf16": (1e-2, 5e-2)}.get(precision, SPLIT_TOL)
     for f in range(2):
         check_end_to_end(res, O.as_tax(rf[f], g), f, tol_i=tol_i, tol_rho=tol_rho)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_largest_serving_frame(pam, torch_cuda, precision):
+    """The largest serving frame's array and record: 256 elements at 0.2 mm on 512 columns,
+    16384 samples at 20 MHz.  A 159-bin band (2.0-2.195 MHz) and 32 depths keep the oracle
+    affordable while the path still runs the 8192-point time FFT, the 256-element lateral
+    DFT and the 512-column fields kernel."""
+    g = synth.cfg5_geometry(256, 20e6, 16384)
+    df = g.fs_hz / g.n_samples
+    g = g.replace(bands_hz=[(2.0e6, 2.0e6 + 159.5 * df)],
+                  depths_m=g.depths_m[np.linspace(0, len(g.depths_m) - 1, 32).astype(int)])
+    rng = np.random.default_rng(77)
+    em = [synth.Emitter(-3 * MM, 30 * MM, "broadband"), synth.Emitter(4 * MM, 45 * MM, "broadband")]
+    rf = synth.render(g, em, rng, snr_db=20.0)
+    res = run(pam, torch_cuda, g, rf[None], precision=precision)
+    ref = O.as_tax(rf, g)
+    assert len(res["bins"]) == len(O.bins(g.fs_hz, g.n_samples, g.bands_hz)) == 159
+    tol_i, tol_rho = (TOL_I, TOL_RHO) if precision == "fp32" else SPLIT_TOL
+    check_end_to_end(res, ref, tol_i=tol_i, tol_rho=tol_rho)

@@ -75,8 +75,9 @@ def test_precision_cfg2_reduced(env, precision):
 
 def test_mixed_record_lengths_on_one_plan(env):
     """64 frames of the cfg1 array with record lengths drawn from {2048, 4096, 8192} on one
-    8192-sample plan, one launch per record length.  Split results are checked against the
-    FP32 path on every frame and against the oracle on one frame of each length."""
+    8192-sample plan, one launch per record length.  Every form is checked against the
+    FP64 oracle on the first frame of each length (FP32: 1e-5 / 1e-4; split BF16 and split
+    FP16: 1e-3 / 1e-3), and the split forms against the FP32 path on every frame."""
     torch, pam = env
     g = synth.cfg3_geometry()
     frames = [synth.cfg3_frame(s) for s in range(64)]
@@ -85,14 +86,17 @@ def test_mixed_record_lengths_on_one_plan(env):
     for n_t in lengths:
         idx = [i for i, fr in enumerate(frames) if fr.shape[-1] == n_t]
         rf = np.stack([frames[i] for i in idx])
-        img32, rho32 = gpu_run(env, g, rf, "fp32")
-        for prec in ("split_bf16", "split_fp16"):
-            img, rho = gpu_run(env, g, rf, prec)
-            for k in range(len(idx)):
-                e = float(np.linalg.norm(img[k] - img32[k]) / np.linalg.norm(img32[k]))
-                assert e <= 1e-3 and float(np.abs(rho[k] - rho32[k]).max()) <= 1e-3
         ref = O.as_tax(rf[0], g.replace(n_samples=n_t))
+        img32, rho32 = gpu_run(env, g, rf, "fp32")
         e_i, e_r = errors(img32[0], rho32[0], ref)
         print(f"n_t={n_t} ({len(idx)} frames): fp32 vs oracle relL2(I)={e_i:.3e} max|d rho_n|={e_r:.3e}",
               flush=True)
         assert e_i <= 1e-5 and e_r <= 1e-4
+        for prec in ("split_bf16", "split_fp16"):
+            img, rho = gpu_run(env, g, rf, prec)
+            e_i, e_r = errors(img[0], rho[0], ref)
+            print(f"n_t={n_t}: {prec} vs oracle relL2(I)={e_i:.3e} max|d rho_n|={e_r:.3e}", flush=True)
+            assert e_i <= 1e-3 and e_r <= 1e-3
+            for k in range(len(idx)):
+                e = float(np.linalg.norm(img[k] - img32[k]) / np.linalg.norm(img32[k]))
+                assert e <= 1e-3 and float(np.abs(rho[k] - rho32[k]).max()) <= 1e-3

@@ -27,7 +27,22 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-30))
 
 
-@pytest.mark.parametrize("levels,H,W,weighted", [(2, 32, 64, False), (3, 32, 128, False), (2, 32, 64, True)])
+# BF16 rounding of an operand has relative RMS error 2^-9 / sqrt(3); every 3x3
+# convolution of the forward pass rounds its input activations and every one of the
+# backward pass rounds its incoming gradient, and independent rounding errors add in
+# quadrature.  A parameter gradient therefore carries a relative error of about
+# u sqrt(2 n_conv) with n_conv = 2 (2 levels - 1) + 1 convolutions (head included);
+# the bound is 6 times that (ReLU and max-pool decisions near ties flip a few paths).
+U_BF16 = 2.0 ** -9 / np.sqrt(3.0)
+
+
+def grad_tolerance(levels: int) -> float:
+    n_conv = 2 * (2 * levels - 1) + 1
+    return 6.0 * U_BF16 * np.sqrt(2 * n_conv)
+
+
+@pytest.mark.parametrize("levels,H,W,weighted", [(2, 32, 64, False), (3, 32, 128, False), (2, 32, 64, True),
+                                                 (4, 16, 256, False)])
 def test_unet_forward_and_gradients_match_reference(env, levels, H, W, weighted):
     torch, nn, S = env
     B = 2
@@ -71,8 +86,9 @@ def test_unet_forward_and_gradients_match_reference(env, levels, H, W, weighted)
         if k == "enc0a.w":
             gg, gref = gg[:, :2], gref[:, :2]          # padded input channels carry no signal
         cos = float(np.sum(gg * gref) / (np.linalg.norm(gg) * np.linalg.norm(gref) + 1e-30))
-        print(f"{k}: rel {rel(gg, gref):.3e} cos {cos:.5f}", flush=True)
-        assert cos > 0.99 and rel(gg, gref) < 0.1, k
+        tol = grad_tolerance(levels)
+        print(f"{k}: rel {rel(gg, gref):.3e} cos {cos:.6f} (bound {tol:.3e})", flush=True)
+        assert rel(gg, gref) < tol and cos > 1.0 - tol ** 2 / 2, k
 
 
 def test_adam_matches_definition(env):
