@@ -19,6 +19,7 @@ Prints ONE JSON line on stdout:
     processes on the host while the GPU legs run;
   * the mixed-record-length workload (64 frames of 2048/4096/8192 samples on one
     8192-sample plan) per form, with its error against the oracle per length;
+  * the paper's comparison beamformer (FD-TEA-TAX) on the same frames;
   * the NCC-mask surrogate, the paper-shape context timings, host-copy-inclusive
     throughput, and a serving leg (Poisson arrivals at 100 / 1,000 / 5,000 frames/s
     over a fixed horizon);
@@ -460,6 +461,36 @@ def pcie_inclusive(geom, rf_host, precision, steps, dev):
             "steps": steps, "copies": "RF host->device and image device->host per launch, pinned host memory"}
 
 
+def fd_tea_entry(geom, rf, fps_as: float, steps: int, n_frames: int = 8) -> dict:
+    """The paper's comparison beamformer (frequency-domain delay-and-sum with the same TAX
+    weighting, pam_fd_tea_tax) on the first frames of the same batch, FP32, timed with
+    events on the stream it runs on."""
+    import torch
+    from paper_2412_02413_amd import pam
+    x = rf[:n_frames]
+    F = x.shape[0]
+    plan = pam.pam_plan(geom, 0, "fp32")
+    try:
+        img = torch.empty((F, geom.n_z, geom.n_x), device=x.device)
+        nn_ = torch.empty_like(img)
+        ws = pam.alloc_workspace(plan, F, geom.n_samples, x.device)
+        pam.pam_fd_tea_tax(plan, x, img, nn_, None, ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            pam.pam_fd_tea_tax(plan, x, img, nn_, None, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    finally:
+        pam.pam_destroy(plan)
+    fps = F / (ms * 1e-3)
+    return {"frames_per_s": round(fps, 2), "ms_per_frame": round(ms / F, 4), "frames_per_launch": F,
+            "as_tax_fp32_over_fd_tea": round(fps_as / fps, 2),
+            "paper_context": "RTX 4090: FD-TEA-TAX 17.3 ms vs AS-TAX 9.8 ms per image (Appendix, Table III)"}
+
+
 def serving_entry(precision: str, horizon_s: float, loads=(100.0, 1000.0, 5000.0)) -> dict:
     """Continuous-batching server under Poisson arrivals: for each offered load, requests
     arrive over `horizon_s` seconds; batches are admitted until horizon + 2 s, after which
@@ -661,6 +692,8 @@ def main():
                 log(f"surrogate, split BF16 propagation: {sur['with_split_bf16_propagation']}")
         else:
             log(f"surrogate weights not found at {args.surrogate}: no surrogate entry")
+    fdt = fd_tea_entry(geom, rf, fps, max(2, args.steps // 10))
+    log(f"FD-TEA-TAX: {fdt}")
     pcie = pcie_inclusive(geom, rf_host, args.precision, max(3, args.steps // 4), dev)
     log(f"with host copies: {pcie}")
     stages_roof = stage_rooflines(geom, n_sel, F, main_res["layout"], stage_ms)
@@ -730,6 +763,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "mixed_record_lengths": mixed,
+        "fd_tea_tax": fdt,
         "surrogate": sur,
         "pcie_inclusive": pcie,
         "paper_shape": pshape,

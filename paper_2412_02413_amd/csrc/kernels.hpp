@@ -1,7 +1,7 @@
 // Device kernels of the AS-TAX hot path for gfx950 (CDNA4, wave64).
 //
 //   k1_time_fft   F_t of every channel (Eq. 1): real FFT of n_t samples as an
-//                 n_t/2-point complex radix-2 FFT in LDS, then the in-band bins.
+//                 n_t/2-point complex Stockham FFT (radix 8) in LDS, then the in-band bins.
 //   k2_lateral    apodization (Pattern-m masks) + lateral DFT F_x (Eq. 1) per
 //                 (frame, bin), folded into the coefficients of a real DFT basis.
 //   k3_fields     the propagator exp(i z kz) of Eq. 2 (FP64 phase, FP32 sin/cos)
@@ -59,10 +59,19 @@ __device__ __forceinline__ float2 propagator(double z, double kzc, int zero_evan
 }
 
 // --------------------------------------------------------------------------
-// K1: time FFT.  One workgroup per (channel, frame).  x[2n] + i x[2n+1] is
-// transformed as an M = n_t/2 point complex FFT (bit-reversed load, in-place
-// radix-2 decimation in time in LDS), then X[k] = E[k] + e^{-2 pi i k/n_t} O[k]
-// with E/O the transforms of the even/odd samples recovered from Z[k], Z[M-k].
+// K1: time FFT.  One workgroup (256 threads) per (channel, frame).  The n_t real
+// samples are read as M = n_t/2 complex values z[n] = x[2n] + i x[2n+1] and
+// transformed by a Stockham auto-sort FFT: passes of radix 8 (then one of radix 4
+// or 2 for the rest), each butterfly j of a pass reading z[j + r M/R], r < R,
+// applying the twiddles e^{-2 pi i r k / (Ns R)} (k = j mod Ns, Ns = the size
+// already transformed) and writing its R outputs at (j - k) R + k + r Ns, so the
+// result lands in natural order with no bit reversal.  The first pass reads its
+// operands straight from global memory (coalesced: consecutive threads take
+// consecutive j); every pass keeps all of a thread's operands in registers
+// between the workgroup barrier that ends the reads and the writes.  At 4096
+// samples that is 4 passes instead of 11 radix-2 stages.  Finally
+// X[k] = E[k] + e^{-2 pi i k/n_t} O[k] with E/O the transforms of the even/odd
+// samples recovered from Z[k] and Z[M-k].
 // --------------------------------------------------------------------------
 struct K1Args {
   const float* rf;        // [F][L][n_t]
@@ -72,33 +81,109 @@ struct K1Args {
   int32_t L, n_t, log2m, tw_stride, n_sel;
 };
 
-__global__ __launch_bounds__(256) void k1_time_fft(K1Args a) {
-  extern __shared__ float2 z[];  // [M]
-  const int l = blockIdx.x, f = blockIdx.y;
-  const int M = a.n_t >> 1;
-  const float2* src = reinterpret_cast<const float2*>(a.rf + ((size_t)f * a.L + l) * a.n_t);
-  for (int n = threadIdx.x; n < M; n += blockDim.x) {
-    const unsigned r = __brev((unsigned)n) >> (32 - a.log2m);
-    z[r] = src[n];
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // times -i
+
+// in-place forward DFTs of 2, 4 and 8 points (e^{-2 pi i / R})
+__device__ __forceinline__ void dft2(float2* v) {
+  const float2 t = v[0];
+  v[0] = cadd(t, v[1]);
+  v[1] = csub(t, v[1]);
+}
+__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+  const float2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3), a3 = mul_mi(csub(v1, v3));
+  v0 = cadd(a0, a2);
+  v2 = csub(a0, a2);
+  v1 = cadd(a1, a3);
+  v3 = csub(a1, a3);
+}
+__device__ __forceinline__ void dft8(float2* v) {
+  // even and odd halves, then the radix-2 combination with w8^k, w8 = e^{-2 pi i / 8}
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  const float r2 = 0.70710678118654752f;
+  o1 = make_float2(r2 * (o1.x + o1.y), r2 * (o1.y - o1.x));        // (1 - i)/sqrt2
+  o2 = mul_mi(o2);                                                    // -i
+  o3 = make_float2(r2 * (o3.y - o3.x), -r2 * (o3.x + o3.y));       // (-1 - i)/sqrt2
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+// One Stockham pass of radix R over M points; EPT = elements per thread, so each
+// thread runs EPT / R butterflies j = tid + 256 w.  Operands come from global memory
+// on the first pass (Ns = 1) and from LDS afterwards.
+template <int R, int EPT>
+__device__ __forceinline__ void stockham_pass(const float2* src, float2* z, int M, int Ns, int tid) {
+  constexpr int PER = EPT / R;
+  const int nbf = M / R;
+  float2 v[PER][R];
+#pragma unroll
+  for (int w = 0; w < PER; ++w) {
+    const int j = tid + 256 * w;
+    if (j < nbf) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[w][r] = Ns == 1 ? src[j + r * nbf] : z[j + r * nbf];
+    }
+  }
+  if (Ns > 1) __syncthreads();   // every read of this pass is done before any write
+#pragma unroll
+  for (int w = 0; w < PER; ++w) {
+    const int j = tid + 256 * w;
+    if (j < nbf) {
+      const int k = j & (Ns - 1);
+      if (Ns > 1) {
+        // w1 = e^{-2 pi i k / (Ns R)} from the hardware sine/cosine (argument in cycles,
+        // an exact dyadic fraction), its higher powers by products
+        const float c = (float)k / (float)(Ns * R);
+        const float2 w1 = make_float2(__builtin_amdgcn_cosf(c), -__builtin_amdgcn_sinf(c));
+        float2 wr = w1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[w][r] = cmul(v[w][r], wr);
+          if (r + 1 < R) wr = cmul(wr, w1);
+        }
+      }
+      if constexpr (R == 8) dft8(v[w]);
+      else if constexpr (R == 4) dft4(v[w][0], v[w][1], v[w][2], v[w][3]);
+      else dft2(v[w]);
+      const int idx = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[idx + r * Ns] = v[w][r];
+    }
   }
   __syncthreads();
-  for (int half = 1; half < M; half <<= 1) {
-    // twiddle e^{-2 pi i pos / (2 half)} = tw[pos * (n_t / (2 half)) * tw_stride]
-    const int step = (a.n_t / (2 * half)) * a.tw_stride;
-    for (int bf = threadIdx.x; bf < (M >> 1); bf += blockDim.x) {
-      const int pos = bf & (half - 1);
-      const int i0 = ((bf - pos) << 1) + pos;
-      const int i1 = i0 + half;
-      const float2 w = a.tw[pos * step];
-      const float2 u = z[i0];
-      const float2 v = cmul(z[i1], w);
-      z[i0] = cadd(u, v);
-      z[i1] = csub(u, v);
-    }
-    __syncthreads();
+}
+
+// EPT = elements per thread = max(8, M / 256).  One-dimensional grid of L F
+// workgroups; consecutive workgroups go round-robin to the 8 XCDs, so the index is
+// remapped to give each XCD runs of consecutive channels of a frame: their bin writes
+// (stride L) then fill the same cache lines of one L2.
+template <int EPT>
+__global__ __launch_bounds__(256) void k1_time_fft(K1Args a) {
+  extern __shared__ float2 z[];  // [M]
+  const int G = gridDim.x;
+  int bid = blockIdx.x;
+  if ((G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
+  const int l = bid % a.L, f = bid / a.L;
+  const int M = a.n_t >> 1;
+  const int tid = threadIdx.x;
+  const float2* src = reinterpret_cast<const float2*>(a.rf + ((size_t)f * a.L + l) * a.n_t);
+  for (int Ns = 1; Ns < M;) {
+    const int R = (M / Ns >= 8) ? 8 : ((M / Ns == 4) ? 4 : 2);
+    if (R == 8) stockham_pass<8, EPT>(src, z, M, Ns, tid);
+    else if (R == 4) stockham_pass<4, EPT>(src, z, M, Ns, tid);
+    else stockham_pass<2, EPT>(src, z, M, Ns, tid);
+    Ns *= R;
   }
   float2* dst = a.spectra + (size_t)f * a.n_sel * a.L + l;
-  for (int b = threadIdx.x; b < a.n_sel; b += blockDim.x) {
+  for (int b = tid; b < a.n_sel; b += 256) {
     const int k = a.ksel[b];               // 0 < k < M
     const float2 zk = z[k];
     const float2 zc = make_float2(z[M - k].x, -z[M - k].y);

@@ -698,7 +698,15 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   // K1: time FFT, one workgroup per (channel, frame)
   {
     pam::K1Args a{rf, spectra, p->d_tw, lv->d_ksel, p->L, n_t, ilog2(n_t / 2), lv->stride, lv->n_sel};
-    hipLaunchKernelGGL(pam::k1_time_fft, dim3(p->L, F), dim3(256), (size_t)(n_t / 2) * sizeof(float2), stream, a);
+    const size_t lds = (size_t)(n_t / 2) * sizeof(float2);
+    const int M = n_t / 2;
+    const unsigned blocks = (unsigned)(p->L * F);
+    if (M <= 2048)
+      hipLaunchKernelGGL(pam::k1_time_fft<8>, dim3(blocks), dim3(256), lds, stream, a);
+    else if (M == 4096)
+      hipLaunchKernelGGL(pam::k1_time_fft<16>, dim3(blocks), dim3(256), lds, stream, a);
+    else
+      hipLaunchKernelGGL(pam::k1_time_fft<32>, dim3(blocks), dim3(256), lds, stream, a);
     if (hipGetLastError() != hipSuccess || !mark(1)) return PAM_ERR_DEVICE;
   }
   // K2: lateral DFT + fold, one workgroup per (bin, frame)
