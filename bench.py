@@ -23,6 +23,8 @@ Prints ONE JSON line on stdout:
   * the NCC-mask surrogate, the paper-shape context timings, host-copy-inclusive
     throughput, and a serving leg (Poisson arrivals at 100 / 1,000 / 5,000 frames/s
     over a fixed horizon);
+  * the evaluation harness on the HIP path: apodization-pattern sweep (ISNR, NNCC
+    centroid), two-source Rayleigh dips, uneven-strength regional peaks (AS, AS-TAX, AS^3);
   * the oracle timed on the host CPU (all cores and one thread; a reported
     baseline, not the target).
 Diagnostics go to stderr.
@@ -560,6 +562,8 @@ def main():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false", help="skip the mixed-record-length leg")
     ap.add_argument("--serving-horizon", type=float, default=1.5,
                     help="seconds of Poisson arrivals per offered load (0 skips the serving leg)")
+    ap.add_argument("--no-evaluation", dest="evaluation", action="store_false",
+                    help="skip the pattern-selection / resolution / uneven-strength harness")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with plain device copies of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -701,6 +705,15 @@ def main():
     if pshape:
         log(f"paper shape: {pshape}")
     serving = serving_entry(args.precision, args.serving_horizon) if args.serving_horizon > 0 else None
+    evaluation = None
+    if args.evaluation:
+        from paper_2412_02413_amd import evaluate as EV
+        t0 = time.perf_counter()
+        evaluation = {"pattern_sweep": EV.pattern_sweep(n_frames=8, precision=args.precision),
+                      "resolution": EV.resolution(n_frames=4, precision=args.precision),
+                      "uneven_strength": EV.uneven_strength(n_frames=4, precision=args.precision)}
+        log(f"evaluation harness in {time.perf_counter() - t0:.1f} s: chosen patterns "
+            f"{[v['chosen_m'] for v in evaluation['pattern_sweep']['methods'].values()]}")
     if args.copy_calibration:
         copy_calibration(dev)
     ev.close()
@@ -768,6 +781,7 @@ def main():
         "pcie_inclusive": pcie,
         "paper_shape": pshape,
         "serving": serving,
+        "evaluation": evaluation,
     }
     print(json.dumps(rec), flush=True)
 

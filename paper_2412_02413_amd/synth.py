@@ -324,6 +324,50 @@ def paper_frame(seed: int, n_bins: int = 690) -> np.ndarray:
     return render(g, em, rng, band=(3 * MHZ, 15 * MHZ), snr_db=20.0)
 
 
+def tunnel_frame(seed: int, geom: Optional[Geometry] = None, snr_db: Optional[float] = 20.0,
+                 z_mm: float = 40.0, half_width_mm: float = 2.5, diameter_mm: float = 5.0,
+                 n_sources: int = 6) -> Tuple[np.ndarray, List[Emitter]]:
+    """Cavitation in a tunnel lying in the image plane (stand-in for a wall-less flow phantom
+    imaged with the array parallel to the tunnel): stable and inertial emitters inside the
+    tunnel's cross-section under the focal region, |x| <= half_width, |z - z_mm| <= d/2.
+    Paper-shape array by default."""
+    g = paper_geometry(690) if geom is None else geom
+    rng = np.random.default_rng(seed)
+    em = [Emitter(rng.uniform(-half_width_mm, half_width_mm) * MM,
+                  (z_mm + rng.uniform(-diameter_mm / 2, diameter_mm / 2)) * MM,
+                  str(rng.choice(["stable", "inertial"])))
+          for _ in range(n_sources)]
+    return render(g, em, rng, snr_db=snr_db), em
+
+
+def bubble_pair_frame(seed: int, p1_mm: Tuple[float, float], p2_mm: Tuple[float, float],
+                      geom: Optional[Geometry] = None, snr_db: Optional[float] = 20.0,
+                      f_drive_hz: float = 1.0 * MHZ, f_centre_hz: float = 8.9 * MHZ,
+                      frac_bw: float = 0.67) -> np.ndarray:
+    """Two bubbles driven by one excitation (stand-in for the Marmottant-model pair of the
+    resolution appendix): each radiates harmonics of the drive frequency inside the
+    geometry's band with its own random amplitudes and phases (slightly different bubble
+    sizes), delayed exactly per channel and shaped by a Gaussian receive response of the
+    array (centre 8.9 MHz, 67 % fractional bandwidth at half amplitude, the CL15-7 figures
+    the appendix states).  Paper-shape array by default."""
+    g = paper_geometry(690) if geom is None else geom
+    rng = np.random.default_rng(seed)
+    n_t = g.n_samples
+    lo, hi = g.bands_hz[0]
+    t = np.arange(n_t) / g.fs_hz
+    sig = np.zeros((g.n_elements, n_t))
+    hs = [h for h in range(1, int(hi // f_drive_hz) + 1) if lo <= h * f_drive_hz <= hi]
+    sigma = frac_bw * f_centre_hz / 2.0 / np.sqrt(2.0 * np.log(2.0))
+    resp = np.exp(-((np.array(hs, float) * f_drive_hz - f_centre_hz) ** 2) / (2.0 * sigma ** 2))
+    for (x, z) in (p1_mm, p2_mm):
+        tau = _delays(g, Emitter(x * MM, z * MM, "stable"))
+        amp = resp * rng.uniform(0.5, 1.0, len(hs))
+        ph = rng.uniform(0, 2 * np.pi, len(hs))
+        for a, p_, h in zip(amp, ph, hs):
+            sig += a * np.cos(2 * np.pi * h * f_drive_hz * (t[None, :] - tau[:, None]) + p_)
+    return _add_noise(sig, snr_db, rng).astype(np.float32)
+
+
 def batch(gen, seeds: Sequence[int]) -> np.ndarray:
     frames = []
     for s in seeds:
