@@ -105,6 +105,8 @@ typedef struct {
   double eps;                /* NCC floor, 0 < eps < 1 (0 means 1e-3)                     */
   pam_precision_t precision;
   pam_evanescent_t evanescent;
+  int32_t coherence;         /* 1: also accumulate adjacent-pixel cross-spectra (see below);
+                                needs n_sub = 1, n_x = 256 and an even n_depths; else 0       */
 } pam_geometry_t;
 
 /* Sizes a plan settles on, for callers that size their own buffers. */
@@ -123,7 +125,11 @@ typedef struct {
  *            two for FP16 operands (scale 1 otherwise)
  *   scales   float32   [F][n_sel]             1 / (power-of-two scale of coeffs)
  *   accum    float32   [n_split][F][n_acc][n_z][N_x] partial sums over disjoint bin
- *            ranges; channels S_1..S_nsub then C_12, C_23, C_31 (n_sub = 3) or C_12
+ *            ranges; channels S_1..S_nsub then C_12, C_23, C_31 (n_sub = 3) or C_12;
+ *            with coherence (n_sub = 1): S, then Re and Im of the lateral pair sum
+ *            G_x(z, x) = sum_w p(z, x) conj(p(z, x ^ 1)) and of the axial pair sum
+ *            G_z(z, x) = sum_w p(z, x) conj(p(z ^ 1, x)) (pairs of adjacent columns 2j, 2j+1
+ *            and of adjacent depths 2i, 2i+1), n_acc = 5
  *   energy   float32   [F][n_z][N_x]          sum_w |sum_i p_i|^2
  *   weight   float32   [F][n_z][N_x]          weight before normalisation
  * n_sel is the number of plan bins on the call's record-length grid. */

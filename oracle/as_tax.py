@@ -265,6 +265,29 @@ def as_tax(rf: np.ndarray, geom, chunk: int = 16) -> Dict[str, np.ndarray]:
     return dict(I=I, rho_n=rho_n, rho=rho, w=w, E=E, S=S, C=C)
 
 
+def pair_cross_spectra(rf: np.ndarray, geom, chunk: int = 16) -> Dict[str, np.ndarray]:
+    """Full-aperture field sums with adjacent-pixel partners (inputs of the surrogate's
+    phase-coherence features): with p the full-aperture field (plain AS, Eq. 3),
+    S = sum_w |p|^2, G_x[z, x] = sum_w p[z, x] conj(p[z, x ^ 1]) over pairs of adjacent
+    columns (2j, 2j + 1) and G_z[z, x] = sum_w p[z, x] conj(p[z ^ 1, x]) over pairs of
+    adjacent depths (2i, 2i + 1).  Needs an even number of columns and of depths."""
+    g = geom.replace(n_sub=1, apod=np.ones((1, geom.n_elements), np.uint8))
+    nz, nx = len(geom.depths_m), geom.n_x
+    if nz % 2 or nx % 2:
+        raise ValueError("pairs need an even number of depths and of columns")
+    xi = np.arange(nx) ^ 1
+    zi = np.arange(nz) ^ 1
+    S = np.zeros((nz, nx))
+    Gx = np.zeros((nz, nx), dtype=np.complex128)
+    Gz = np.zeros((nz, nx), dtype=np.complex128)
+    for _, p in fields(rf, g, chunk):
+        q = p[0]                                            # [c][n_z][N]
+        S += np.sum(np.abs(q) ** 2, axis=0)
+        Gx += np.sum(q * np.conj(q[:, :, xi]), axis=0)
+        Gz += np.sum(q * np.conj(q[:, zi, :]), axis=0)
+    return dict(S=S, Gx=Gx, Gz=Gz)
+
+
 def as_image(rf: np.ndarray, geom, chunk: int = 16) -> np.ndarray:
     """Plain AS image of Eq. 3 with the full aperture: sum over bins of |p|^2."""
     g = geom.replace(n_sub=1, apod=np.ones((1, geom.n_elements), np.uint8))

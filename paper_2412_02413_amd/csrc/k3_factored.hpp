@@ -119,11 +119,12 @@ struct FfTw {
 
 // Lane (c, h) of a wave holds depth d0 + c/16 and columns x = c%16 + 16 x2,
 // x2 = 8(v/4) + 4h + v%4 for v = 0..7.
-template <int NSUB>
+template <int NSUB, bool COH = false>
 __device__ __forceinline__ void ff_store(const K3Args& a, int sp, int f, int d0, int lane,
                                          const float (&accS)[NSUB][8],
-                                         const float (&accC)[AccCount<NSUB>::pairs > 0 ? AccCount<NSUB>::pairs : 1][8]) {
-  constexpr int NA = AccCount<NSUB>::total;
+                                         const float (&accC)[AccCount<NSUB>::pairs > 0 ? AccCount<NSUB>::pairs : 1][8],
+                                         const float (*accG)[8] = nullptr) {
+  constexpr int NA = COH ? 5 : AccCount<NSUB>::total;
   constexpr int NP = AccCount<NSUB>::pairs;
   const int c = lane & 31, h = lane >> 5;
   const int row = d0 + (c >> 4);
@@ -137,6 +138,10 @@ __device__ __forceinline__ void ff_store(const K3Args& a, int sp, int f, int d0,
     for (int i = 0; i < NSUB; ++i) dst[i * plane + x] = accS[i][v];
 #pragma unroll
     for (int p = 0; p < NP; ++p) dst[(NSUB + p) * plane + x] = accC[p][v];
+    if constexpr (COH) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) dst[(1 + g) * plane + x] = accG[g][v];
+    }
   }
 }
 
@@ -180,8 +185,12 @@ struct FfOps {
   }
 };
 
-template <typename T, int PASSES, int NSUB>
+// COH (n_sub = 1 only): the back half also accumulates, per pixel, the cross-spectra
+// with its lateral pair partner (column x ^ 1, the adjacent lane) and its axial pair
+// partner (depth 2i <-> 2i + 1, the lane 16 away), G = sum over bins of p conj(p').
+template <typename T, int PASSES, int NSUB, bool COH = false>
 __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
+  static_assert(!COH || NSUB == 1, "pair cross-spectra come with the full-aperture sums only");
   constexpr bool F32 = std::is_same<T, float>::value;
   constexpr bool SCALED = std::is_same<T, _Float16>::value;   // keep K2's scale through stage 3
   constexpr int NP = AccCount<NSUB>::pairs;
@@ -224,12 +233,15 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
   const FfTw tw(a, lane);
   float accS[NSUB][8];
   float accC[NP > 0 ? NP : 1][8];
+  float accG[COH ? 4 : 1][8];      // Re, Im of the lateral, then of the axial pair sums
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
 #pragma unroll
     for (int i = 0; i < NSUB; ++i) accS[i][v] = 0.f;
 #pragma unroll
     for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][v] = 0.f;
+#pragma unroll
+    for (int g = 0; g < (COH ? 4 : 1); ++g) accG[g][v] = 0.f;
   }
 
   // products of one stage: C_i = W x operand_i for every sub-aperture
@@ -358,6 +370,15 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
       } else if constexpr (NSUB == 2) {
         accC[0][v] = fmaf(pr[0], pr[1], fmaf(pim[0], pim[1], accC[0][v]));
       }
+      if constexpr (COH) {
+        // partner fields: column x ^ 1 sits in lane ^ 1, depth zz ^ 1 in lane ^ 16
+        const float lr = __shfl_xor(pr[0], 1), li = __shfl_xor(pim[0], 1);
+        const float zr = __shfl_xor(pr[0], 16), zi = __shfl_xor(pim[0], 16);
+        accG[0][v] = fmaf(pr[0], lr, fmaf(pim[0], li, accG[0][v]));
+        accG[1][v] = fmaf(pim[0], lr, fmaf(-pr[0], li, accG[1][v]));
+        accG[2][v] = fmaf(pr[0], zr, fmaf(pim[0], zi, accG[2][v]));
+        accG[3][v] = fmaf(pim[0], zr, fmaf(-pr[0], zi, accG[3][v]));
+      }
     }
   };
 
@@ -377,7 +398,7 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
     if (more) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB>());
     __syncthreads();
   }
-  ff_store<NSUB>(a, wg.sp, f, d0, lane, accS, accC);
+  ff_store<NSUB, COH>(a, wg.sp, f, d0, lane, accS, accC, accG);
 }
 
 }  // namespace pam

@@ -362,6 +362,7 @@ struct K4Args {
   float* image;         // [F][pix]
   float* nncc;          // [F][pix] or null
   int32_t pix, F, n_split, n_sub, n_blk;
+  int32_t n_acc;        // accumulator channels per frame (S, C and, with coherence, the pair sums)
   double eps;
 };
 
@@ -369,13 +370,14 @@ __global__ __launch_bounds__(256) void k4_weight(K4Args a) {
   __shared__ float red[256];
   const int f = blockIdx.y;
   const int p = blockIdx.x * 256 + threadIdx.x;
-  const int na = a.n_sub == 3 ? 6 : (a.n_sub == 2 ? 3 : 1);
+  const int na = a.n_acc;                                        // channel stride
+  const int nr = a.n_sub == 3 ? 6 : (a.n_sub == 2 ? 3 : 1);     // channels read here
   float wv = 0.f;
   if (p < a.pix) {
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int s = 0; s < a.n_split; ++s) {
       const float* src = a.accum + ((size_t)s * a.F + f) * na * a.pix + p;
-      for (int c = 0; c < na; ++c) v[c] += (double)src[(size_t)c * a.pix];
+      for (int c = 0; c < nr; ++c) v[c] += (double)src[(size_t)c * a.pix];
     }
     double E, w;
     if (a.n_sub == 1) {

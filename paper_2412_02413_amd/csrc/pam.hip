@@ -93,6 +93,7 @@ struct pam_plan_s {
   int L = 0, n_t = 0, N = 0, n_z = 0, n_sub = 0, n_bins = 0;
   double eps = 1e-3;
   int precision = 0, zero_evanescent = 0;
+  int coherence = 0;          // adjacent-pixel cross-spectra with the n_sub = 1 sums
   std::vector<int32_t> bins;  // k on the plan grid
   std::vector<Level> levels;
   // device tables
@@ -165,6 +166,8 @@ pam_status_t validate(const pam_geometry_t* g) {
   if (!(g->eps >= 0.0 && g->eps < 1.0)) return PAM_ERR_INVALID_ARG;
   if (g->precision < PAM_PREC_FP32 || g->precision > PAM_PREC_FP16) return PAM_ERR_INVALID_ARG;
   if (g->evanescent != PAM_EVAN_DECAY && g->evanescent != PAM_EVAN_ZERO) return PAM_ERR_INVALID_ARG;
+  if (g->coherence != 0 && g->coherence != 1) return PAM_ERR_INVALID_ARG;
+  if (g->coherence && (g->n_sub != 1 || g->n_x != 256 || (g->n_depths & 1))) return PAM_ERR_UNSUPPORTED;
   return PAM_OK;
 }
 
@@ -241,7 +244,7 @@ const Level* level_for(const pam_plan_s* p, int n_t) {
   return nullptr;
 }
 
-int n_acc(int n_sub) { return n_sub == 3 ? 6 : (n_sub == 2 ? 3 : 1); }
+int n_acc(int n_sub, int coherence = 0) { return n_sub == 3 ? 6 : (n_sub == 2 ? 3 : (coherence ? 5 : 1)); }
 
 pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layout_t* out) {
   const Level* lv = level_for(p, n_t);
@@ -254,14 +257,14 @@ pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layou
   L.spectra = o;  o = align256(o + (size_t)F * lv->n_sel * p->L * sizeof(float2));
   L.coeffs = o;   o = align256(o + (size_t)F * lv->n_sel * p->n_sub * p->N * sizeof(float2));
   L.scales = o;   o = align256(o + (size_t)F * lv->n_sel * sizeof(float));
-  L.accum = o;    o = align256(o + (size_t)s.n_split * F * n_acc(p->n_sub) * pix * sizeof(float));
+  L.accum = o;    o = align256(o + (size_t)s.n_split * F * n_acc(p->n_sub, p->coherence) * pix * sizeof(float));
   L.energy = o;   o = align256(o + (size_t)F * pix * sizeof(float));
   L.weight = o;   o = align256(o + (size_t)F * pix * sizeof(float));
   L.blockmax = o; o = align256(o + (size_t)F * n_blk * sizeof(float));
   L.total = std::max<size_t>(o, 256);
   L.n_sel = lv->n_sel;
   L.n_split = s.n_split;
-  L.n_acc = n_acc(p->n_sub);
+  L.n_acc = n_acc(p->n_sub, p->coherence);
   *out = L;
   return PAM_OK;
 }
@@ -378,7 +381,18 @@ hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& 
 }
 
 hipError_t launch_k3(int precision, int n_sub, const LaunchShape& s, const pam::K3Args& a, int blocks,
-                     hipStream_t st) {
+                     hipStream_t st, int coherence) {
+  if (coherence) {
+    using namespace pam;
+    const size_t lds = k3ff_lds<1>();
+    switch (precision) {
+      case PAM_PREC_SPLIT_BF16: return launch_fused(k3ff<__bf16, 3, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      case PAM_PREC_SPLIT_FP16: return launch_fused(k3ff<_Float16, 3, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      case PAM_PREC_BF16: return launch_fused(k3ff<__bf16, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      case PAM_PREC_FP16: return launch_fused(k3ff<_Float16, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      default: return launch_fused(k3ff<float, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+    }
+  }
   switch (n_sub) {
     case 3: return launch_shape<3>(precision, s, a, blocks, st);
     case 2: return launch_shape<2>(precision, s, a, blocks, st);
@@ -426,6 +440,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
   p->eps = g->eps > 0.0 ? g->eps : 1e-3;
   p->precision = g->precision;
   p->zero_evanescent = g->evanescent == PAM_EVAN_ZERO;
+  p->coherence = g->coherence;
   p->bins = ks;
   const int L = p->L, N = p->N, HQ = N / 2 + 1;
 
@@ -750,14 +765,15 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
                   lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw, lv->d_ev};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
     if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
-    if (launch_k3(p->precision, p->n_sub, s, a, (int)blocks, stream) != hipSuccess || !mark(3))
+    if (launch_k3(p->precision, p->n_sub, s, a, (int)blocks, stream, p->coherence) != hipSuccess || !mark(3))
       return PAM_ERR_DEVICE;
   }
   // K4: NCC / weight / energy, then NNCC and image
   {
     const int pix = p->n_z * p->N;
     const int n_blk = (pix + 255) / 256;
-    pam::K4Args a{accum, energy, weight, blockmax, rho_pairs, image, nncc, pix, F, W.n_split, p->n_sub, n_blk, p->eps};
+    pam::K4Args a{accum, energy, weight, blockmax, rho_pairs, image, nncc, pix, F, W.n_split, p->n_sub, n_blk,
+                  W.n_acc, p->eps};
     hipLaunchKernelGGL(pam::k4_weight, dim3(n_blk, F), dim3(256), 0, stream, a);
     if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
     hipLaunchKernelGGL(pam::k4_image, dim3(n_blk, F), dim3(256), 0, stream, a);

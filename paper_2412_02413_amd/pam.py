@@ -35,7 +35,7 @@ class GeometryC(C.Structure):
                 ("n_depths", C.c_int32), ("depths_m", C.POINTER(C.c_double)), ("n_x", C.c_int32),
                 ("lateral", C.c_int), ("n_sub", C.c_int32), ("apod", C.POINTER(C.c_uint8)),
                 ("pattern_m", C.c_int32), ("eps", C.c_double), ("precision", C.c_int),
-                ("evanescent", C.c_int)]
+                ("evanescent", C.c_int), ("coherence", C.c_int32)]
 
 
 class PlanInfoC(C.Structure):
@@ -128,6 +128,7 @@ def geometry_struct(geom, precision: Optional[str] = None):
     g.eps = geom.eps
     g.precision = PRECISIONS[precision or getattr(geom, "precision", "fp32")]
     g.evanescent = EVANESCENT[geom.evanescent]
+    g.coherence = int(getattr(geom, "coherence", 0))
     return g, keep
 
 

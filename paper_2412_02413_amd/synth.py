@@ -63,6 +63,7 @@ class Geometry:
     apod: Optional[np.ndarray] = None   # explicit (n_sub, L) 0/1 masks, overrides pattern_m
     eps: float = 1e-3
     evanescent: str = "decay"     # "decay" or "zero"
+    coherence: int = 0            # 1: adjacent-pixel cross-spectra with the full-aperture sums
 
     def replace(self, **kw) -> "Geometry":
         return dataclasses.replace(self, **kw)

@@ -431,3 +431,43 @@ def test_esa_isnr_centroid_hand_image():
     J = np.array([[0.0, 10.0, 8.0], [0.0, 0.0, 0.0]])
     cx, cz = O.centroid(J, np.array([0.0, 1.0, 2.0]), np.array([5.0, 6.0]), 0.7)
     assert abs(cx - 1.4444444444444444) < 1e-15 and cz == 5.0
+
+
+# ---------------------------------------------------------------- pair cross-spectra (surrogate features)
+
+def test_pair_cross_spectra_plane_wave_closed_form():
+    # the plane wave of test_plane_wave_closed_form: p[d, j] = (n_t/2) e^{i kx0 x_j} e^{i z_d kz}, so
+    # G_x = (n_t/2)^2 e^{i kx0 (x_j - x_{j^1})} and G_z = (n_t/2)^2 e^{i kz (z_d - z_{d^1})}
+    L, n_t, fs, c, pitch = 16, 128, 20e6, 1540.0, 0.3e-3
+    k0, q0 = 20, 3
+    z = np.array([0.0, 4e-3, 9e-3, 9.5e-3])
+    g = synth.Geometry(n_elements=L, pitch_m=pitch, fs_hz=fs, c_mps=c, n_samples=n_t,
+                       bands_hz=[(k0 * fs / n_t, k0 * fs / n_t)], depths_m=z, n_x=L, lateral="pad", n_sub=1)
+    kx0 = 2 * np.pi * q0 / (L * pitch)
+    xl = (np.arange(L) - (L - 1) / 2) * pitch
+    n = np.arange(n_t)
+    rf = np.cos(2 * np.pi * k0 * n[None, :] / n_t + kx0 * xl[:, None])
+    kzv = math.sqrt((2 * np.pi * (k0 * fs / n_t) / c) ** 2 - kx0 ** 2)
+    r = O.pair_cross_spectra(rf, g)
+    a2 = (n_t / 2) ** 2
+    j = np.arange(L)
+    want_x = a2 * np.exp(1j * kx0 * (xl[j] - xl[j ^ 1]))
+    d = np.arange(len(z))
+    want_z = a2 * np.exp(1j * kzv * (z[d] - z[d ^ 1]))
+    np.testing.assert_allclose(r["Gx"], np.broadcast_to(want_x, r["Gx"].shape), atol=1e-8 * a2)
+    np.testing.assert_allclose(r["Gz"], np.broadcast_to(want_z[:, None], r["Gz"].shape), atol=1e-8 * a2)
+    np.testing.assert_allclose(r["S"], a2, rtol=1e-10)
+
+
+def test_pair_cross_spectra_pairing_and_bound():
+    g = small_cfg1(n_depths=10)
+    rf = synth.cfg1_frame(16)
+    r = O.pair_cross_spectra(rf, g)
+    S, Gx, Gz = r["S"], r["Gx"], r["Gz"]
+    x1 = np.arange(g.n_x) ^ 1
+    z1 = np.arange(10) ^ 1
+    np.testing.assert_allclose(Gx[:, x1], np.conj(Gx), rtol=1e-12, atol=1e-12 * S.max())
+    np.testing.assert_allclose(Gz[z1, :], np.conj(Gz), rtol=1e-12, atol=1e-12 * S.max())
+    assert np.all(np.abs(Gx) ** 2 <= S * S[:, x1] * (1 + 1e-12))
+    assert np.all(np.abs(Gz) ** 2 <= S * S[z1, :] * (1 + 1e-12))
+    np.testing.assert_allclose(S, O.as_image(rf, g), rtol=1e-12)

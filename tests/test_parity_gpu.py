@@ -369,3 +369,48 @@ def test_stage_time_fft_record_lengths(pam, torch_cuda, n_t):
         err = np.abs(X[f].T - ref["X"]).max() / np.abs(ref["X"]).max()
         print(f"n_t={n_t}: max |dX| / max |X| = {err:.2e}", flush=True)
         assert err < 2e-6, err
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_coherence_pair_sums(pam, torch_cuda, precision):
+    """Adjacent-pixel cross-spectra (the coherence channels of an n_sub = 1 plan) against the
+    oracle's pair sums: 38 depths (three 16-depth tiles, ragged tail), full-size lateral grid,
+    two frames.  The image of such a plan stays the plain AS image."""
+    g = synth.cfg2_geometry()
+    g = g.replace(depths_m=g.depths_m[np.linspace(0, 511, 38).astype(int)], n_sub=1,
+                  apod=np.ones((1, g.n_elements), np.uint8), coherence=1)
+    rf = np.stack([synth.cfg2_frame(310 + s)[0] for s in range(2)])
+    res = run(pam, torch_cuda, g, rf, precision=precision, want_pairs=False)
+    lay = res["layout"]
+    assert lay.n_acc == 5
+    nz, nx = len(g.depths_m), g.n_x
+    acc = ws_view(torch_cuda, res["ws"], lay.accum, lay.n_split * 2 * 5 * nz * nx, np.float32)
+    acc = acc.reshape(lay.n_split, 2, 5, nz, nx).astype(np.float64).sum(axis=0)
+    tol = 2e-5 if precision == "fp32" else 2e-4
+    for f in range(2):
+        ref = O.pair_cross_spectra(rf[f], g)
+        smax = ref["S"].max()
+        gx = acc[f, 1] + 1j * acc[f, 2]
+        gz = acc[f, 3] + 1j * acc[f, 4]
+        e = [float(np.abs(acc[f, 0] - ref["S"]).max() / smax),
+             float(np.abs(gx - ref["Gx"]).max() / smax),
+             float(np.abs(gz - ref["Gz"]).max() / smax)]
+        print(f"frame {f}: max err / max S  S={e[0]:.2e} Gx={e[1]:.2e} Gz={e[2]:.2e}", flush=True)
+        assert max(e) <= tol
+        # normalised coherence where the field is not negligible
+        x1, z1 = np.arange(nx) ^ 1, np.arange(nz) ^ 1
+        live = (ref["S"] > 1e-2 * smax) & (ref["S"][:, x1] > 1e-2 * smax) & (ref["S"][z1, :] > 1e-2 * smax)
+        cx = np.abs(gx) / np.sqrt(acc[f, 0] * acc[f, 0][:, x1])
+        cx_ref = np.abs(ref["Gx"]) / np.sqrt(ref["S"] * ref["S"][:, x1])
+        assert np.abs(cx - cx_ref)[live].max() <= 100 * tol
+        check_end_to_end(res, O.as_tax(rf[f], g), f, *((TOL_I, TOL_RHO) if precision == "fp32" else SPLIT_TOL))
+
+
+def test_coherence_needs_one_subaperture(pam, torch_cuda):
+    g = synth.cfg2_geometry().replace(coherence=1)
+    with pytest.raises(pam.PamError):
+        pam.pam_plan(g, 0, "fp32")
+    g = synth.cfg2_geometry()
+    g = g.replace(depths_m=g.depths_m[:37], n_sub=1, apod=np.ones((1, g.n_elements), np.uint8), coherence=1)
+    with pytest.raises(pam.PamError):
+        pam.pam_plan(g, 0, "fp32")
