@@ -332,7 +332,9 @@ def surrogate_entry(geom, rf, plain_images, fps_plain, precision, steps, warmup,
     against plain AS-TAX's."""
     import torch
     from paper_2412_02413_amd import surrogate as S
-    net, tau = S.UNet.from_weights(path)
+    net, calibration = S.UNet.from_weights(path)
+    cal = calibration.get(S.geometry_key(geom))
+    tau = cal["tau"] if cal else -1.0          # an uncalibrated geometry falls back on every frame
     F = rf.shape[0]
     pipe = S.SurrogatePipeline(geom, net, tau=tau, precision=precision, max_frames=F)
     try:
@@ -352,14 +354,19 @@ def surrogate_entry(geom, rf, plain_images, fps_plain, precision, steps, warmup,
     _, isnr_s = S.image_metrics(image)
     _, isnr_p = S.image_metrics(plain_images)
     fps = F * steps / wall
+    over = rel > cal["bound"] if cal else torch.zeros_like(rel, dtype=torch.bool)
     return {"frames_per_s": round(fps, 2), "ms_per_step": round(1e3 * wall / steps, 3),
-            "speedup_vs_plain": round(fps / fps_plain, 3), "tau": round(tau, 4),
+            "speedup_vs_plain": round(fps / fps_plain, 3),
+            "fallback_rule": "predicted image rel. L2 error > tau (per-geometry split-conformal calibration)",
+            "tau": round(tau, 5), "bound": cal["bound"] if cal else None, "alpha": cal["alpha"] if cal else None,
             "fallback_rate": round(fb / (F * steps), 4),
+            "frames_over_bound": round(float(over.float().mean()), 4),
             "image_rel_l2_vs_plain_mean": round(float(rel.mean()), 4),
             "image_rel_l2_vs_plain_p95": round(float(rel.quantile(0.95)), 4),
             "image_rel_l2_vs_plain_max": round(float(rel.max()), 4),
             "abs_d_isnr_db_mean": round(float((isnr_s - isnr_p).abs().mean()), 3),
-            "network": f"U-Net {net.levels} levels, {net.base} base channels, BF16 operands, FP32 accumulation",
+            "network": f"U-Net {net.levels} levels, {net.base} base channels, {net.n_feat} input features "
+                       "(energy, adjacent-pixel coherence), BF16 operands, FP32 accumulation",
             "weights": os.path.relpath(path, ROOT)}
 
 
@@ -555,7 +562,7 @@ def main():
     ap.add_argument("--variants", default="split_bf16,split_fp16,bf16,fp16",
                     help="other precision forms measured beside the main one (comma list, '' for none)")
     ap.add_argument("--surrogate", default=os.path.join(ROOT, "paper_2412_02413_amd", "weights",
-                                                        "surrogate_l4_b32.safetensors"),
+                                                        "surrogate_l4_b32_coh.safetensors"),
                     help="surrogate weights measured beside plain AS-TAX ('' for none)")
     ap.add_argument("--no-paper-shape", dest="paper_shape", action="store_false",
                     help="skip the paper-shape (690 / 128 bins, 300 x 256) context timing")

@@ -109,6 +109,26 @@ pam_status_t pam_nn_pack_weights(const float* w, int32_t c_in, int32_t c_out, vo
  * channel 1 = E / max E, channels 2..31 = 0 (max over each frame). */
 pam_status_t pam_nn_features(const float* energy, int32_t batch, int64_t pixels, void* out, void* hip_stream);
 
+/* Network input from the accumulator channels of a full-aperture plan built with
+ * coherence = 1 (pam.h): accum FP32 [n_split][batch][5][n_z][n_x] (S, Re G_x, Im G_x,
+ * Re G_z, Im G_z), consecutive splits split_stride floats apart (ignored when n_split = 1).
+ * Writes energy FP32 [batch][n_z][n_x] = S summed over the splits and BF16
+ * [batch][n_z * n_x][32] features:
+ *   0: clamp(log10(S / max S) / 6 + 1, 0, 1)        1: S / max S
+ *   2-4: |c_x|, Re c_x, Im c_x with c_x = G_x / sqrt(S(z, x0) S(z, x0 + 1)) of the
+ *        column pair (x0, x0 + 1), x0 = x rounded down to even
+ *   5-7: the same for the depth pair (z0, z0 + 1), z0 = z rounded down to even
+ *   8-31: 0
+ * A pair whose energies multiply to 0 has c = 0.  n_z and n_x must be even. */
+pam_status_t pam_nn_coherence_features(const float* accum, int32_t n_split, int64_t split_stride, int32_t batch,
+                                       int32_t n_z, int32_t n_x, void* out, float* energy, void* hip_stream);
+
+/* Predicted relative L2 error of each frame's image mask^2 E when the mask is off by
+ * err per pixel: est[f] = ||2 mask err E|| / ||mask^2 E|| over the frame's pixels (FP64
+ * sums; +inf for an all-zero image).  mask, err, energy FP32 [batch][pixels]. */
+pam_status_t pam_nn_error_estimate(const float* mask, const float* err, const float* energy, int32_t batch,
+                                   int64_t pixels, float* est, void* hip_stream);
+
 /* Per-frame confidence conf[f] = 1 - sum_p E err / sum_p E (energy-weighted mean of
  * the predicted mask error); err, energy FP32 [batch][pixels]. */
 pam_status_t pam_nn_confidence(const float* err, const float* energy, int32_t batch, int64_t pixels, float* conf,

@@ -401,6 +401,98 @@ __global__ __launch_bounds__(1024) void features_kernel(const float* E, int64_t 
   }
 }
 
+// Input features from the adjacent-pixel cross-spectra of a full-aperture field: one
+// workgroup per frame.  Pass 1 sums the channels over the bin splits into the energy
+// (S) and finds its maximum; pass 2 writes the eight feature channels of every pixel.
+// A pair's normalised cross-spectrum is taken at its even member (left column, upper
+// depth), so both pixels of a pair see the same oriented value.
+__global__ __launch_bounds__(1024) void coherence_features_kernel(const float* acc, int32_t n_split, int64_t sstride,
+                                                                  int32_t n_z, int32_t n_x, bf16* out, float* energy) {
+  __shared__ float red[1024];
+  const int64_t f = blockIdx.x;
+  const int64_t P = (int64_t)n_z * n_x;
+  const float* a0 = acc + f * 5 * P;
+  float* e = energy + f * P;
+  auto chan = [&](int c, int64_t p) {
+    float v = 0.f;
+    for (int s = 0; s < n_split; ++s) v += a0[s * sstride + c * P + p];
+    return v;
+  };
+  float m = 0.f;
+  for (int64_t p = threadIdx.x; p < P; p += 1024) {
+    const float v = chan(0, p);
+    e[p] = v;
+    m = fmaxf(m, v);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const float inv = red[0] > 0.f ? 1.f / red[0] : 1.f;
+  auto coh = [&](int64_t q0, int64_t q1, int c, float* o) {   // |c|, Re c, Im c of the pair (q0, q1)
+    const float d = e[q0] * e[q1];
+    if (!(d > 0.f)) {
+      o[0] = o[1] = o[2] = 0.f;
+      return;
+    }
+    const float r = rsqrtf(d);
+    const float re = fminf(fmaxf(chan(c, q0) * r, -1.f), 1.f), im = fminf(fmaxf(chan(c + 1, q0) * r, -1.f), 1.f);
+    o[0] = fminf(sqrtf(re * re + im * im), 1.f);
+    o[1] = re;
+    o[2] = im;
+  };
+  for (int64_t p = threadIdx.x; p < P; p += 1024) {
+    const int x = (int)(p % n_x), z = (int)(p / n_x);
+    const float r = e[p] * inv;
+    float cx[3], cz[3];
+    coh((int64_t)z * n_x + (x & ~1), (int64_t)z * n_x + (x | 1), 1, cx);
+    coh((int64_t)(z & ~1) * n_x + x, (int64_t)(z | 1) * n_x + x, 3, cz);
+    v8bf lo, z8 = {};
+    lo[0] = (bf16)fminf(fmaxf(log10f(fmaxf(r, 1e-30f)) / 6.f + 1.f, 0.f), 1.f);
+    lo[1] = (bf16)r;
+    lo[2] = (bf16)cx[0];
+    lo[3] = (bf16)cx[1];
+    lo[4] = (bf16)cx[2];
+    lo[5] = (bf16)cz[0];
+    lo[6] = (bf16)cz[1];
+    lo[7] = (bf16)cz[2];
+    v8bf* dst = reinterpret_cast<v8bf*>(out + (f * P + p) * 32);
+    dst[0] = lo;
+    dst[1] = z8;
+    dst[2] = z8;
+    dst[3] = z8;
+  }
+}
+
+// Predicted relative L2 error of a frame's image: with the image mask^2 E and a mask
+// off by err per pixel, the image error is about 2 mask err E, so
+// est = ||2 mask err E|| / ||mask^2 E|| (sums in FP64).
+__global__ __launch_bounds__(1024) void error_estimate_kernel(const float* mask, const float* err, const float* E,
+                                                              int64_t P, float* est) {
+  __shared__ double s0[1024], s1[1024];
+  const int64_t f = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t p = threadIdx.x; p < P; p += 1024) {
+    const double m = mask[f * P + p], e = E[f * P + p];
+    const double d = 2.0 * m * (double)err[f * P + p] * e, i = m * m * e;
+    a += d * d;
+    b += i * i;
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s0[threadIdx.x] += s0[threadIdx.x + s];
+      s1[threadIdx.x] += s1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) est[f] = s1[0] > 0.0 ? (float)sqrt(s0[0] / s1[0]) : INFINITY;
+}
+
 // per-frame confidence: 1 - sum_p E[p] err[p] / sum_p E[p]
 __global__ __launch_bounds__(1024) void confidence_kernel(const float* err, const float* E, int64_t P, float* conf) {
   __shared__ float s0[1024], s1[1024];
@@ -582,6 +674,24 @@ pam_status_t pam_nn_features(const float* energy, int32_t batch, int64_t pixels,
   if (!energy || !out || batch < 1 || pixels < 1 || !aligned16(out)) return PAM_ERR_INVALID_ARG;
   hipLaunchKernelGGL(features_kernel, dim3(batch), dim3(1024), 0, static_cast<hipStream_t>(hip_stream), energy, pixels,
                      static_cast<bf16*>(out));
+  return launched();
+}
+
+pam_status_t pam_nn_coherence_features(const float* accum, int32_t n_split, int64_t split_stride, int32_t batch,
+                                       int32_t n_z, int32_t n_x, void* out, float* energy, void* hip_stream) {
+  if (!accum || !out || !energy || n_split < 1 || batch < 1 || n_z < 2 || n_x < 2 || (n_z & 1) || (n_x & 1) ||
+      (n_split > 1 && split_stride < (int64_t)batch * 5 * n_z * n_x) || !aligned16(out))
+    return PAM_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(coherence_features_kernel, dim3(batch), dim3(1024), 0, static_cast<hipStream_t>(hip_stream), accum,
+                     n_split, split_stride, n_z, n_x, static_cast<bf16*>(out), energy);
+  return launched();
+}
+
+pam_status_t pam_nn_error_estimate(const float* mask, const float* err, const float* energy, int32_t batch,
+                                   int64_t pixels, float* est, void* hip_stream) {
+  if (!mask || !err || !energy || !est || batch < 1 || pixels < 1) return PAM_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(error_estimate_kernel, dim3(batch), dim3(1024), 0, static_cast<hipStream_t>(hip_stream), mask, err,
+                     energy, pixels, est);
   return launched();
 }
 

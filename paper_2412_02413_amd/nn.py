@@ -33,6 +33,8 @@ def lib():
             "pam_nn_features": [vp, i32, i64, vp, vp],
             "pam_nn_confidence": [vp, vp, i32, i64, vp, vp],
             "pam_nn_apply_mask": [vp, vp, vp, i64, vp],
+            "pam_nn_coherence_features": [vp, i32, i64, i32, i32, i32, vp, vp, vp],
+            "pam_nn_error_estimate": [vp, vp, vp, i32, i64, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -117,3 +119,12 @@ def confidence(err, energy, batch, pixels, conf, stream=None):
 
 def apply_mask(mask, energy, image, stream=None):
     _call("pam_nn_apply_mask", _p(mask), _p(energy), _p(image), mask.numel(), _s(stream))
+
+
+def coherence_features(accum, n_split, split_stride, batch, n_z, n_x, out, energy, stream=None):
+    _call("pam_nn_coherence_features", _p(accum), n_split, split_stride, batch, n_z, n_x, _p(out), _p(energy),
+          _s(stream))
+
+
+def error_estimate(mask, err, energy, batch, pixels, est, stream=None):
+    _call("pam_nn_error_estimate", _p(mask), _p(err), _p(energy), batch, pixels, _p(est), _s(stream))

@@ -4,10 +4,16 @@ AS-TAX forms its image as I = rho_n^2 * E (Eq. 11) where E is the energy of the
 summed sub-aperture fields and rho_n the normalised TAX weight (Eq. 10), which
 costs three angular-spectrum propagations.  With complementary masks, E equals
 the plain full-aperture AS image (Eq. 3), which costs one.  The surrogate is a
-U-Net that predicts rho_n from the full-aperture energy alone, plus a per-pixel
-estimate of its own error; a frame whose energy-weighted predicted error is too
-high (confidence below a threshold) falls back to plain AS-TAX.  Plain AS-TAX
-on the GPU generates the training targets and judges the result.
+U-Net that predicts rho_n from that one propagation: its energy and the
+normalised cross-spectra of adjacent pixels (how coherent the field is from
+column to column and from depth to depth over the band), plus a per-pixel
+estimate of its own error.  The error estimate gives a predicted relative L2
+error of the frame's image; a frame whose prediction exceeds a per-geometry
+threshold falls back to plain AS-TAX.  The threshold is calibrated on held-out
+frames of that geometry (split conformal on the ratio of true to predicted
+error) so that an accepted frame exceeds a stated image-error bound with
+probability at most alpha.  Plain AS-TAX on the GPU generates the training
+targets and judges the result.
 
 Every numerical step runs in the HIP library: the reconstructions through
 pam_as_tax, the network through the pam_nn_* kernels.  This module owns the
@@ -26,7 +32,8 @@ import numpy as np
 
 from . import nn, pam, synth
 
-C_FEAT = 32   # input channels of the first convolution (2 features, zero padded)
+C_FEAT = 32   # input channels of the first convolution (N_FEAT features, zero padded)
+N_FEAT = 8    # energy (2) and adjacent-pixel coherence (6) features
 
 
 @dataclass
@@ -41,10 +48,10 @@ class UNet:
     include/pam_nn.h): two 3x3 convolutions + ReLU per level, 2x2 max pooling, nearest 2x
     upsampling with skip concatenation [upsampled, skip], a 1x1 head with two outputs."""
 
-    def __init__(self, levels: int = 4, base: int = 32, seed: int = 0, device: str = "cuda"):
+    def __init__(self, levels: int = 4, base: int = 32, seed: int = 0, device: str = "cuda", n_feat: int = N_FEAT):
         import torch
         self.torch = torch
-        self.levels, self.base = levels, base
+        self.levels, self.base, self.n_feat = levels, base, n_feat
         self.device = torch.device(device)
         self.ch = [base * 2 ** l for l in range(levels)]
         self.specs: List[ConvSpec] = []
@@ -59,9 +66,9 @@ class UNet:
         rng = np.random.default_rng(seed)
         host = {}
         for s in self.specs:
-            fan_in = 9 * (2 if s.name == "enc0a" else s.c_in)
+            live = n_feat if s.name == "enc0a" else s.c_in
+            fan_in = 9 * live
             w = np.zeros((9, s.c_in, s.c_out))
-            live = 2 if s.name == "enc0a" else s.c_in
             w[:, :live, :] = rng.standard_normal((9, live, s.c_out)) * math.sqrt(2.0 / fan_in)
             host[s.name + ".w"] = w
             host[s.name + ".b"] = np.zeros(s.c_out)
@@ -98,20 +105,24 @@ class UNet:
 
     @classmethod
     def from_weights(cls, path, device: str = "cuda"):
-        """Network and threshold from an inference-weights file written by the driver."""
+        """Network and its per-geometry calibration from an inference-weights file."""
+        import json
         from safetensors import safe_open
         with safe_open(path, framework="pt") as f:
             meta = f.metadata()
-            net = cls(int(meta["levels"]), int(meta["base"]), device=device)
+            net = cls(int(meta["levels"]), int(meta["base"]), device=device, n_feat=int(meta["n_feat"]))
             for k in net.params:
                 net.params[k].copy_(f.get_tensor(k))
         net.pack()
-        return net, float(meta["tau"])
+        return net, json.loads(meta["calibration"])
 
-    def save_weights(self, path, tau: float):
+    def save_weights(self, path, calibration: Dict[str, dict]):
+        import json
         from safetensors.torch import save_file
         save_file({k: v.detach().cpu().contiguous() for k, v in self.params.items()}, path,
-                  metadata={"levels": str(self.levels), "base": str(self.base), "tau": repr(float(tau))})
+                  metadata={"levels": str(self.levels), "base": str(self.base), "n_feat": str(self.n_feat),
+                            "features": "energy + adjacent-pixel coherence",
+                            "calibration": json.dumps(calibration)})
 
     def load_state_dict(self, sd):
         for k in self.params:
@@ -280,9 +291,15 @@ def generate_rf(seeds: Sequence[int], workers: int = 0, kind: str = "train") -> 
     return np.stack(frames)
 
 
+def geometry_key(geom) -> str:
+    """Calibration key of an array / record / grid set-up."""
+    bands = "+".join(f"{lo:.6g}-{hi:.6g}" for lo, hi in geom.bands_hz)
+    return (f"L{geom.n_elements}_p{geom.pitch_m:.6g}_fs{geom.fs_hz:.6g}_nt{geom.n_samples}_b{bands}"
+            f"_x{geom.n_x}{geom.lateral}_z{len(geom.depths_m)}")
+
+
 class Teacher:
-    """Plain AS-TAX on the GPU: the full-aperture energy E (equal to the AS image for
-    complementary masks) and the NNCC rho_n of each frame."""
+    """Plain AS-TAX on the GPU: the image and NNCC rho_n of each frame."""
 
     def __init__(self, geom, precision: str = "fp32", max_frames: int = 64):
         import torch
@@ -299,57 +316,101 @@ class Teacher:
         lay = pam.pam_workspace_layout(self.plan, F, self.geom.n_samples)
         img = torch.empty((F, self.plan.n_z, self.plan.n_x), device=rf.device)
         nncc = torch.empty_like(img)
-        ws = self.ws[:lay.total]
-        pam.pam_as_tax(self.plan, rf, img, nncc, None, ws)
-        pix = self.plan.n_z * self.plan.n_x
-        energy = ws[lay.energy:lay.energy + F * pix * 4].view(torch.float32).view(F, self.plan.n_z, self.plan.n_x)
-        return energy.clone(), nncc, img
+        pam.pam_as_tax(self.plan, rf, img, nncc, None, self.ws[:lay.total])
+        return nncc, img
+
+    def close(self):
+        pam.pam_destroy(self.plan)
+
+
+class FullAperture:
+    """One full-aperture propagation with the adjacent-pixel cross-spectra (an n_sub = 1
+    plan with coherence): the energy E (the plain AS image) and the accumulator channels
+    S, G_x, G_z left in the workspace."""
+
+    def __init__(self, geom, precision: str = "fp32", max_frames: int = 64):
+        import torch
+        self.torch = torch
+        self.geom = geom.replace(n_sub=1, apod=np.ones((1, geom.n_elements), np.uint8), coherence=1)
+        self.plan = pam.pam_plan(self.geom, 0, precision)
+        self.max_frames = max_frames
+        self.ws = pam.alloc_workspace(self.plan, max_frames, geom.n_samples)
+        self.P = self.plan.n_z * self.plan.n_x
+
+    def __call__(self, rf):
+        """Returns (E [F][n_z][n_x], accum [n_split * F * 5 * P] FP32 view, n_split)."""
+        torch = self.torch
+        F = rf.shape[0]
+        assert F <= self.max_frames
+        lay = pam.pam_workspace_layout(self.plan, F, self.geom.n_samples)
+        E = torch.empty((F, self.plan.n_z, self.plan.n_x), device=rf.device)
+        pam.pam_as_tax(self.plan, rf, E, None, None, self.ws[:lay.total])
+        assert lay.n_acc == 5
+        acc = self.ws[lay.accum: lay.accum + lay.n_split * F * 5 * self.P * 4].view(torch.float32)
+        return E, acc, lay.n_split
+
+    def reduced(self, rf):
+        """Accumulator channels summed over the bin splits: FP32 [F][5][n_z][n_x]."""
+        E, acc, n_split = self(rf)
+        F = rf.shape[0]
+        a = acc.view(n_split, F, 5, self.plan.n_z, self.plan.n_x)
+        return a[0].clone() if n_split == 1 else a.sum(0)
 
     def close(self):
         pam.pam_destroy(self.plan)
 
 
 def build_dataset(seeds, geom, chunk: int = 64, workers: int = 16, log=None, kind: str = "train"):
-    """Energies and NNCC targets (FP32 device tensors [n][n_z][n_x]) of the given frames."""
+    """Accumulator channels A (FP32 [n][5][n_z][n_x]: S = E, G_x, G_z of the full aperture)
+    and NNCC targets R (FP32 [n][n_z][n_x]) of the given frames, as device tensors."""
     import torch
     t = Teacher(geom, max_frames=chunk)
-    E, R = [], []
+    fa = FullAperture(geom, max_frames=chunk)
+    A, R = [], []
     try:
         for i in range(0, len(seeds), 512):
             rf = generate_rf(seeds[i:i + 512], workers, kind)
             for j in range(0, rf.shape[0], chunk):
                 x = torch.from_numpy(rf[j:j + chunk]).cuda()
-                e, r, _ = t(x)
-                E.append(e)
-                R.append(r)
+                r, _ = t(x)
+                A.append(fa.reduced(x))
+                R.append(r.clone())
             if log:
                 log(f"dataset: {min(i + 512, len(seeds))}/{len(seeds)} frames")
     finally:
         torch.cuda.synchronize()
         t.close()
-    return torch.cat(E), torch.cat(R)
+        fa.close()
+    return torch.cat(A), torch.cat(R)
+
+
+def features(A, feats, energy):
+    """Network input and energy of frames A (FP32 [b][5][n_z][n_x], one split)."""
+    b, _, H, W = A.shape
+    nn.coherence_features(A, 1, 0, b, H, W, feats, energy)
 
 
 # ----------------------------------------------------------------------------
 # Training and inference
 # ----------------------------------------------------------------------------
 
-def train(net: UNet, E, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 0, log=None, log_every=50,
+def train(net: UNet, A, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 0, log=None, log_every=50,
           mix: float = 0.1):
-    """Adam on batches drawn from (E, R); the loss weights each pixel by its share of the
+    """Adam on batches drawn from (A, R); the loss weights each pixel by its share of the
     frame's energy (blended with a uniform share `mix`), where the mask shapes the image."""
     torch = net.torch
-    n, H, W = E.shape
+    n, _, H, W = A.shape
     feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
+    e = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
     wts = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
     rng = np.random.default_rng(seed)
     hist = []
     t0 = time.perf_counter()
     for it in range(steps):
         idx = torch.as_tensor(rng.choice(n, size=batch, replace=False), device=net.device)
-        e = E.index_select(0, idx).contiguous()
+        a = A.index_select(0, idx).contiguous()
         r = R.index_select(0, idx).contiguous()
-        nn.features(e, batch, H * W, feats)
+        features(a, feats, e)
         nn.loss_weights(e, batch, H * W, mix, wts)
         net.forward(feats, batch, H, W)
         loss = net.loss_backward(r, wts)
@@ -363,57 +424,96 @@ def train(net: UNet, E, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: i
     return hist
 
 
-def predict(net: UNet, E, batch: int = 8):
-    """Mask, predicted error and per-frame confidence for energies E [n][H][W]."""
+def _infer(net: UNet, feats, e, b, H, W):
     torch = net.torch
-    n, H, W = E.shape
+    m, er = net.forward(feats[:b], b, H, W)
+    est = torch.empty(b, dtype=torch.float32, device=net.device)
+    nn.error_estimate(m, er, e[:b], b, H * W, est)
+    return m, er, est
+
+
+def predict(net: UNet, A, batch: int = 8):
+    """Mask, per-pixel predicted error and predicted image error of frames A [n][5][H][W]."""
+    torch = net.torch
+    n, _, H, W = A.shape
     feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
-    masks, errs, confs = [], [], []
+    e = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
+    masks, errs, ests = [], [], []
     for i in range(0, n, batch):
         b = min(batch, n - i)
-        e = E[i:i + b].contiguous()
-        nn.features(e, b, H * W, feats)
-        m, er = net.forward(feats[:b], b, H, W)
-        c = torch.empty(b, dtype=torch.float32, device=net.device)
-        nn.confidence(er, e, b, H * W, c)
+        features(A[i:i + b].contiguous(), feats, e)
+        m, er, est = _infer(net, feats, e, b, H, W)
         masks.append(m.clone())
         errs.append(er.clone())
-        confs.append(c)
-    return torch.cat(masks), torch.cat(errs), torch.cat(confs)
+        ests.append(est)
+    return torch.cat(masks), torch.cat(errs), torch.cat(ests)
+
+
+def calibrate(est, actual, bound: float, alpha: float) -> dict:
+    """Threshold on the predicted image error for a stated bound.
+
+    Split conformal on r = actual / predicted error over n calibration frames: q is the
+    ceil((n + 1)(1 - alpha))-th smallest r, and a frame is accepted when its predicted
+    error is at most tau = bound / q.  For a new frame exchangeable with the calibration
+    frames, P(r <= q) >= 1 - alpha, and an accepted frame with r <= q has an image error
+    of at most q * (bound / q) = bound, so the probability that a frame is accepted yet
+    exceeds the bound is at most alpha."""
+    est = np.asarray(est, dtype=np.float64)
+    actual = np.asarray(actual, dtype=np.float64)
+    n = len(est)
+    r = np.sort(np.where(est > 0, actual / np.maximum(est, 1e-300), np.inf))
+    k = int(math.ceil((n + 1) * (1 - alpha)))
+    q = float(r[k - 1]) if k <= n else math.inf
+    tau = bound / q if q > 0 else math.inf
+    accepted = est <= tau
+    return {"tau": tau, "q": q, "bound": bound, "alpha": alpha, "n": n,
+            "calibration_accept_rate": float(accepted.mean()),
+            "calibration_accepted_over_bound": float((accepted & (actual > bound)).mean())}
 
 
 class SurrogatePipeline:
-    """Surrogate AS-TAX: one full-aperture propagation (n_sub = 1 plan) + network mask;
-    frames whose confidence is below tau are recomputed with plain AS-TAX."""
+    """Surrogate AS-TAX: one full-aperture propagation with the pair cross-spectra + network
+    mask; frames whose predicted image error exceeds tau are recomputed with plain AS-TAX
+    (tau < 0: every frame; tau = inf: none)."""
 
-    def __init__(self, geom, net: UNet, tau: float, precision: str = "fp32", max_frames: int = 64):
+    def __init__(self, geom, net: UNet, tau: float, precision: str = "fp32", max_frames: int = 64,
+                 batch: int = 8):
         import torch
         self.torch = torch
         self.geom, self.net, self.tau = geom, net, tau
-        g1 = geom.replace(n_sub=1, apod=np.ones((1, geom.n_elements), np.uint8))
-        self.plan1 = pam.pam_plan(g1, 0, precision)
-        self.ws1 = pam.alloc_workspace(self.plan1, max_frames, geom.n_samples)
+        self.fa = FullAperture(geom, precision, max_frames)
         self.teacher = Teacher(geom, precision, max_frames)
+        self.batch = batch
+        H, W = self.fa.plan.n_z, self.fa.plan.n_x
+        self.feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
+        self.e = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
 
     def __call__(self, rf):
         torch = self.torch
         F = rf.shape[0]
-        H, W = self.plan1.n_z, self.plan1.n_x
-        E = torch.empty((F, H, W), device=rf.device)
-        pam.pam_as_tax(self.plan1, rf, E, None, None, self.ws1)      # plain AS image = E
-        mask, err, conf = predict(self.net, E, batch=min(8, F))
+        H, W = self.fa.plan.n_z, self.fa.plan.n_x
+        P = H * W
+        E, acc, n_split = self.fa(rf)                       # plain AS image = E
+        mask = torch.empty_like(E)
+        est = torch.empty(F, dtype=torch.float32, device=rf.device)
+        for i in range(0, F, self.batch):
+            b = min(self.batch, F - i)
+            nn.coherence_features(acc[i * 5 * P:], n_split, F * 5 * P, b, H, W, self.feats, self.e)
+            m, _, es = _infer(self.net, self.feats, self.e, b, H, W)
+            mask[i:i + b].copy_(m)
+            est[i:i + b].copy_(es)
         image = torch.empty_like(E)
         nn.apply_mask(mask, E, image)
-        fallback = (conf < self.tau).cpu().numpy()
+        fallback = (est > self.tau).cpu().numpy()
         if fallback.any():
             idx = np.nonzero(fallback)[0]
             sel = torch.as_tensor(idx, device=rf.device)
-            _, _, img3 = self.teacher(rf.index_select(0, sel).contiguous())
+            _, img3 = self.teacher(rf.index_select(0, sel).contiguous())
             image.index_copy_(0, sel, img3)
-        return image, mask, conf, fallback
+        return image, mask, est, fallback
 
     def close(self):
-        pam.pam_destroy(self.plan1)
+        self.fa.close()
         self.teacher.close()
 
 
@@ -434,21 +534,54 @@ def image_metrics(I):
     return n_in, isnr
 
 
-def compare(E, R, mask, label):
-    """Image error and metric differences of I = mask^2 E against AS-TAX's I = rho_n^2 E."""
-    torch = __import__("torch")
+def image_errors(E, R, mask):
+    """Relative L2 error of each frame's image mask^2 E against AS-TAX's rho_n^2 E."""
     I_ref = R * R * E
     I = mask * mask * E
-    rel = ((I - I_ref).flatten(1).norm(dim=1) / I_ref.flatten(1).norm(dim=1)).double()
-    esa_r, isnr_r = image_metrics(I_ref)
-    esa, isnr = image_metrics(I)
+    return ((I - I_ref).flatten(1).norm(dim=1) / I_ref.flatten(1).norm(dim=1)).double()
+
+
+def compare(E, R, mask, label):
+    """Image error and metric differences of I = mask^2 E against AS-TAX's I = rho_n^2 E."""
+    rel = image_errors(E, R, mask)
+    esa_r, isnr_r = image_metrics(R * R * E)
+    esa, isnr = image_metrics(mask * mask * E)
     w = E / E.flatten(1).sum(1)[:, None, None]
     ml1 = ((mask - R).abs() * w).flatten(1).sum(1).double()
     return {"form": label, "image_rel_l2_mean": float(rel.mean()), "image_rel_l2_p95": float(rel.quantile(0.95)),
+            "image_rel_l2_max": float(rel.max()),
             "mask_l1_energy_weighted_mean": float(ml1.mean()),
             "mask_l1_mean": float((mask - R).abs().flatten(1).mean(1).mean()),
             "abs_d_isnr_db_mean": float((isnr - isnr_r).abs().mean()),
             "abs_d_esa_rel_mean": float(((esa - esa_r).abs() / esa_r).mean())}
+
+
+def evaluate(net, A, R, cal: dict):
+    """Held-out frames against a calibration: fallback rate, the fraction of frames accepted
+    yet over the bound, and the images with fallback, alone and of the baselines."""
+    import torch
+    E = A[:, 0]
+    m, _, est = predict(net, A)
+    err = image_errors(E, R, m)
+    fb = est > cal["tau"]
+    accepted = ~fb
+    m_fb = torch.where(fb[:, None, None], R, m)
+    as3 = E / E.flatten(1).max(1).values[:, None, None]
+    est_d = est.double()
+    return {"frames": int(E.shape[0]), "tau": cal["tau"], "bound": cal["bound"], "alpha": cal["alpha"],
+            "fallback_rate": float(fb.float().mean()),
+            "accepted_over_bound": float((accepted & (err > cal["bound"])).float().mean()),
+            "accepted_error_mean": float(err[accepted].mean()) if bool(accepted.any()) else None,
+            "predicted_vs_actual_error_corr": float(torch.corrcoef(torch.stack([est_d, err]))[0, 1]),
+            "results": [compare(E, R, m_fb, "surrogate with fallback"), compare(E, R, m, "surrogate alone"),
+                        compare(E, R, torch.ones_like(m), "plain AS (weight 1)"),
+                        compare(E, R, as3, "AS^3 self-mask (appendix)")]}
+
+
+def calibration_for(net, A, R, bound, alpha):
+    m, _, est = predict(net, A)
+    err = image_errors(A[:, 0], R, m)
+    return calibrate(est.cpu().numpy(), err.cpu().numpy(), bound, alpha)
 
 
 def main(argv=None):
@@ -456,9 +589,9 @@ def main(argv=None):
     import json
     import sys
     import torch
-    ap = argparse.ArgumentParser(description="train and evaluate the NCC-mask surrogate")
+    ap = argparse.ArgumentParser(description="train, calibrate and evaluate the NCC-mask surrogate")
     ap.add_argument("--train", type=int, default=20000)
-    ap.add_argument("--val", type=int, default=500)
+    ap.add_argument("--val", type=int, default=1000, help="calibration frames of the training geometry")
     ap.add_argument("--eval", type=int, default=2000)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=8)
@@ -466,12 +599,14 @@ def main(argv=None):
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--base", type=int, default=32)
     ap.add_argument("--workers", type=int, default=16)
-    ap.add_argument("--fallback-rate", type=float, default=0.1, help="validation fallback fraction fixing tau")
+    ap.add_argument("--bound", type=float, default=0.25, help="image relative L2 error bound")
+    ap.add_argument("--alpha", type=float, default=0.05, help="allowed rate of accepted frames over the bound")
     ap.add_argument("--headline-train", type=int, default=0,
                     help="benchmark-workload frames (128 elements) added to the training set")
-    ap.add_argument("--headline-eval", type=int, default=64)
+    ap.add_argument("--headline-val", type=int, default=500, help="calibration frames of the benchmark geometry")
+    ap.add_argument("--headline-eval", type=int, default=128)
     ap.add_argument("--out", default="", help="training checkpoint (parameters and Adam state)")
-    ap.add_argument("--weights", default="", help="inference weights (parameters and threshold, safetensors)")
+    ap.add_argument("--weights", default="", help="inference weights (parameters and calibration, safetensors)")
     args = ap.parse_args(argv)
 
     def log(*a):
@@ -480,68 +615,51 @@ def main(argv=None):
     geom = synth.cfg4_geometry()
     hgeom = synth.cfg2_geometry()
     rep = {"geometry": "64 elements, 1024 samples at 20 MHz, 205 bins (1-5 MHz), 512 x 256 grid",
-           "network": f"U-Net {args.levels} levels, {args.base} base channels, BF16 operands, FP32 accumulation",
+           "network": f"U-Net {args.levels} levels, {args.base} base channels, {N_FEAT} input features, "
+                      "BF16 operands, FP32 accumulation",
            "train_frames": args.train, "headline_train_frames": args.headline_train, "val_frames": args.val,
-           "eval_frames": args.eval, "headline_eval_frames": args.headline_eval, "steps": args.steps,
-           "batch": args.batch, "lr": args.lr}
+           "headline_val_frames": args.headline_val, "eval_frames": args.eval,
+           "headline_eval_frames": args.headline_eval, "steps": args.steps, "batch": args.batch, "lr": args.lr,
+           "bound": args.bound, "alpha": args.alpha}
     t0 = time.perf_counter()
-    E_tr, R_tr = build_dataset(list(range(args.train)), geom, workers=args.workers, log=log)
+    A_tr, R_tr = build_dataset(list(range(args.train)), geom, workers=args.workers, log=log)
     if args.headline_train:
-        Eh, Rh = build_dataset(list(range(3_000_000, 3_000_000 + args.headline_train)), hgeom,
+        Ah, Rh = build_dataset(list(range(3_000_000, 3_000_000 + args.headline_train)), hgeom,
                                workers=args.workers, log=log, kind="headline")
-        E_tr, R_tr = torch.cat([E_tr, Eh]), torch.cat([R_tr, Rh])
-    E_va, R_va = build_dataset(list(range(args.train, args.train + args.val)), geom, workers=args.workers)
-    E_ev, R_ev = build_dataset(list(range(1_000_000, 1_000_000 + args.eval)), geom, workers=args.workers)
+        A_tr, R_tr = torch.cat([A_tr, Ah]), torch.cat([R_tr, Rh])
+        del Ah, Rh
+    A_va, R_va = build_dataset(list(range(args.train, args.train + args.val)), geom, workers=args.workers)
+    A_ev, R_ev = build_dataset(list(range(1_000_000, 1_000_000 + args.eval)), geom, workers=args.workers)
+    Ah_va, Rh_va = build_dataset(list(range(5_000_000, 5_000_000 + args.headline_val)), hgeom,
+                                 workers=args.workers, kind="headline")
+    Ah_ev, Rh_ev = build_dataset(list(range(4_000_000, 4_000_000 + args.headline_eval)), hgeom,
+                                 workers=args.workers, kind="headline")
     rep["dataset_s"] = round(time.perf_counter() - t0, 1)
     log(f"datasets in {rep['dataset_s']} s")
     net = UNet(args.levels, args.base, seed=0)
     t0 = time.perf_counter()
-    hist = train(net, E_tr, R_tr, args.steps, args.batch, args.lr, log=log, log_every=max(1, args.steps // 20))
+    hist = train(net, A_tr, R_tr, args.steps, args.batch, args.lr, log=log, log_every=max(1, args.steps // 20))
     torch.cuda.synchronize()
     rep["train_s"] = round(time.perf_counter() - t0, 1)
     rep["train_ms_per_step"] = round(1e3 * rep["train_s"] / max(1, args.steps), 2)
     rep["loss_history"] = hist
-    # threshold from the validation split
-    _, _, conf_va = predict(net, E_va)
-    tau = float(torch.quantile(conf_va, args.fallback_rate)) if args.fallback_rate > 0 else -1.0
-    rep["tau"] = tau
-    rep["heldout"] = evaluate(net, E_ev, R_ev, tau)
-    # the same network on the benchmark workload (128 elements, 768 bins, same grid)
-    rf_h = torch.from_numpy(generate_rf(list(range(4_000_000, 4_000_000 + args.headline_eval)), args.workers,
-                                        "headline")).cuda()
-    th = Teacher(hgeom, max_frames=64)
-    try:
-        Eh_ev, Rh_ev = [], []
-        for j in range(0, rf_h.shape[0], 64):
-            e, r, _ = th(rf_h[j:j + 64].contiguous())
-            Eh_ev.append(e)
-            Rh_ev.append(r)
-    finally:
-        torch.cuda.synchronize()
-        th.close()
-    rep["headline"] = evaluate(net, torch.cat(Eh_ev), torch.cat(Rh_ev), tau)
+    del A_tr, R_tr
+    cal = {geometry_key(geom): calibration_for(net, A_va, R_va, args.bound, args.alpha),
+           geometry_key(hgeom): calibration_for(net, Ah_va, Rh_va, args.bound, args.alpha)}
+    rep["calibration"] = cal
+    rep["heldout"] = evaluate(net, A_ev, R_ev, cal[geometry_key(geom)])
+    rep["headline"] = evaluate(net, Ah_ev, Rh_ev, cal[geometry_key(hgeom)])
+    rf_h = generate_rf(list(range(4_000_000, 4_000_064)), args.workers, "headline")
     rep["ms_per_frame"] = {"train workload": timing(geom, net, generate_rf(list(range(2_000_000, 2_000_064)),
                                                                              args.workers)),
-                           "benchmark workload": timing(hgeom, net, rf_h[:64].cpu().numpy())}
+                           "benchmark workload": timing(hgeom, net, rf_h)}
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         torch.save(net.state_dict(), args.out)
     if args.weights:
         os.makedirs(os.path.dirname(os.path.abspath(args.weights)), exist_ok=True)
-        net.save_weights(args.weights, tau)
+        net.save_weights(args.weights, cal)
     print(json.dumps(rep), flush=True)
-
-
-def evaluate(net, E, R, tau):
-    import torch
-    m, _, conf = predict(net, E)
-    fb = conf < tau
-    m_fb = torch.where(fb[:, None, None], R, m)
-    as3 = E / E.flatten(1).max(1).values[:, None, None]
-    return {"frames": int(E.shape[0]), "fallback_rate": float(fb.float().mean()),
-            "results": [compare(E, R, m_fb, "surrogate with fallback"), compare(E, R, m, "surrogate alone"),
-                        compare(E, R, torch.ones_like(m), "plain AS (weight 1)"),
-                        compare(E, R, as3, "AS^3 self-mask (appendix)")]}
 
 
 def timing(geom, net, rf_host, reps: int = 5):
@@ -549,7 +667,7 @@ def timing(geom, net, rf_host, reps: int = 5):
     import torch
     rf = torch.from_numpy(np.ascontiguousarray(rf_host)).cuda()
     F = rf.shape[0]
-    pipe = SurrogatePipeline(geom, net, tau=-1.0, max_frames=F)
+    pipe = SurrogatePipeline(geom, net, tau=math.inf, max_frames=F)
     teacher = Teacher(geom, max_frames=F)
     try:
         for _ in range(2):

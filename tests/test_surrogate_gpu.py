@@ -114,22 +114,23 @@ def small_data(env):
     torch, nn, S = env
     from paper_2412_02413_amd import synth
     g = synth.cfg4_geometry()
-    E, R = S.build_dataset(list(range(300)), g, workers=0)
-    E_ev, R_ev = S.build_dataset(list(range(1_000_000, 1_000_040)), g, workers=0)
-    return g, E, R, E_ev, R_ev
+    A, R = S.build_dataset(list(range(300)), g, workers=0)
+    A_ev, R_ev = S.build_dataset(list(range(1_000_000, 1_000_040)), g, workers=0)
+    return g, A, R, A_ev, R_ev
 
 
 def test_training_gains_over_plain_as(env, small_data):
     """A short training run already brings the image much closer to AS-TAX than plain AS
     (the method without the network: weight 1), and the training loss decreases."""
     torch, nn, S = env
-    g, E, R, E_ev, R_ev = small_data
+    g, A, R, A_ev, R_ev = small_data
     net = S.UNet(4, 32, seed=1)
-    hist = S.train(net, E, R, steps=300, batch=8, lr=3e-4, log_every=50)
+    hist = S.train(net, A, R, steps=300, batch=8, lr=3e-4, log_every=50)
     first = np.mean([h[1] for h in hist[:2]])
     last = np.mean([h[1] for h in hist[-2:]])
     assert last < first
-    m, _, _ = S.predict(net, E_ev)
+    m, _, _ = S.predict(net, A_ev)
+    E_ev = A_ev[:, 0]
     sur = S.compare(E_ev, R_ev, m, "surrogate")
     plain = S.compare(E_ev, R_ev, torch.ones_like(m), "AS")
     print(sur, plain, flush=True)
@@ -143,7 +144,7 @@ def test_fallback_reproduces_plain_as_tax(env, small_data):
     g = synth.cfg4_geometry()
     net = S.UNet(4, 32, seed=2)
     rf = torch.from_numpy(S.generate_rf([5, 6, 7])).cuda()
-    pipe = S.SurrogatePipeline(g, net, tau=2.0)     # confidence never reaches 2: every frame falls back
+    pipe = S.SurrogatePipeline(g, net, tau=-1.0)    # predicted errors are >= 0: every frame falls back
     try:
         image, mask, conf, fb = pipe(rf)
         assert fb.all()
@@ -174,3 +175,57 @@ def test_checkpoint_round_trip(env, tmp_path):
     a = a.clone()
     b, _ = other.forward(x, 2, 64, 128)
     assert torch.equal(a, b) and other.step_count == net.step_count
+
+
+def test_coherence_features_definition(env):
+    """The feature kernel against its definition on random accumulator channels split over
+    three bin ranges (the workspace layout of a multi-split launch)."""
+    torch, nn, S = env
+    rng = np.random.default_rng(5)
+    n_split, F, H, W = 3, 2, 6, 64
+    P = H * W
+    # channels built from actual fields so the normalised values lie in [-1, 1]
+    p = rng.standard_normal((n_split, F, 7, H, W)) + 1j * rng.standard_normal((n_split, F, 7, H, W))
+    p[:, :, :, 1, :] = 0.0                                    # a dead depth row: pairs with c = 0
+    acc = np.zeros((n_split, F, 5, H, W))
+    x1, z1 = np.arange(W) ^ 1, np.arange(H) ^ 1
+    acc[:, :, 0] = np.sum(np.abs(p) ** 2, axis=2)
+    gx = np.sum(p * np.conj(p[..., x1]), axis=2)
+    gz = np.sum(p * np.conj(p[..., z1, :]), axis=2)
+    acc[:, :, 1], acc[:, :, 2], acc[:, :, 3], acc[:, :, 4] = gx.real, gx.imag, gz.real, gz.imag
+    dev = torch.from_numpy(acc.astype(np.float32)).cuda()
+    out = torch.zeros((F, H, W, S.C_FEAT), dtype=torch.bfloat16, device="cuda")
+    e = torch.empty((F, H, W), device="cuda")
+    nn.coherence_features(dev.view(-1), n_split, F * 5 * P, F, H, W, out, e)
+    got = out.float().cpu().numpy()
+    a = acc.astype(np.float32).astype(np.float64).sum(0)     # [F][5][H][W]
+    S_ = a[:, 0]
+    np.testing.assert_allclose(e.cpu().numpy(), S_, rtol=1e-6)
+    mx = S_.reshape(F, -1).max(1)[:, None, None]
+    r = S_ / mx
+    want = np.zeros((F, H, W, 8))
+    want[..., 0] = np.clip(np.log10(np.maximum(r, 1e-30)) / 6 + 1, 0, 1)
+    want[..., 1] = r
+    xe, ze = np.arange(W) & ~1, np.arange(H) & ~1
+    d = S_[:, :, xe] * S_[:, :, xe + 1]
+    cx = np.where(d > 0, (a[:, 1] + 1j * a[:, 2])[:, :, xe] / np.sqrt(np.where(d > 0, d, 1)), 0)
+    d = S_[:, ze, :] * S_[:, ze + 1, :]
+    cz = np.where(d > 0, (a[:, 3] + 1j * a[:, 4])[:, ze, :] / np.sqrt(np.where(d > 0, d, 1)), 0)
+    for k, c in ((2, cx), (5, cz)):
+        want[..., k], want[..., k + 1], want[..., k + 2] = np.abs(c), c.real, c.imag
+    np.testing.assert_allclose(got[..., :8], want, atol=1e-2)     # BF16 output
+    assert np.all(got[..., 8:] == 0)
+    assert np.all(got[:, 0:2, :, 5:8] == 0)                         # the pair with the dead row
+
+
+def test_error_estimate_definition(env):
+    torch, nn, S = env
+    rng = np.random.default_rng(6)
+    m, er, E = rng.random((3, 4, 500)), rng.random((3, 4, 500)) * 0.1, rng.random((3, 4, 500)) * 1e6
+    E[2][3] = 0.0
+    t = [torch.tensor(v, dtype=torch.float32).cuda() for v in (m[0], er[0], E[0])]
+    est = torch.empty(4, device="cuda")
+    nn.error_estimate(t[0], t[1], t[2], 4, 500, est)
+    mf, ef, Ef = (v.cpu().numpy().astype(np.float64) for v in t)
+    want = np.linalg.norm(2 * mf * ef * Ef, axis=1) / np.linalg.norm(mf * mf * Ef, axis=1)
+    np.testing.assert_allclose(est.cpu().numpy(), want, rtol=1e-5)
