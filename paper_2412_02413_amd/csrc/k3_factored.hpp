@@ -14,13 +14,24 @@
 // = 32, and 32 independent transforms as the columns of one 32x32 tile.  Executed
 // matrix flops per complex output are 2 x 128 instead of the 4N of a dense DFT.
 //
-// This file serves N = 256 (N1 = N2 = 16).  A wave owns two depths and the full
-// 256 columns: its stage-1 tile has columns (q2, depth) = 16 x 2, its stage-3 tile
-// columns (x1, depth) = 16 x 2.  Between the stages each wave transposes its own
-// twiddled stage-1 results through a private LDS buffer (no workgroup barrier).
-// The accumulators of its 512 pixels (8 per lane) stay in registers over the bins.
-// A workgroup is 8 waves = 16 depths of one frame; it stages each bin's
-// coefficients and kz row in LDS (double-buffered, one barrier per bin).
+// This file serves N = 256 (N1 = N2 = 16, R = 1) and N = 512 (R = 2).  At N = 256 a
+// wave owns two depths and the full 256 columns: its stage-1 tile has columns
+// (q2, depth) = 16 x 2, its stage-3 tile columns (x1, depth) = 16 x 2.  Between the
+// stages each wave transposes its own twiddled stage-1 results through a private LDS
+// buffer (no workgroup barrier).  The accumulators of its 512 pixels (8 per lane)
+// stay in registers over the bins.  A workgroup is 8 waves = 16 depths of one frame;
+// it stages each bin's coefficients and kz row in LDS (double-buffered, one barrier
+// per bin).
+//
+// N = 512 splits the sum by the parity e of q first (radix 2 in frequency):
+//     p(x) = P_0(x mod 256) + e^{2 pi i x / 512} P_1(x mod 256),
+//     P_e(x') = sum_q' A(2 q' + e) e^{2 pi i q' x' / 256},
+// and since e^{2 pi i (x' + 256) / 512} = -e^{2 pi i x' / 512}, the two pixels x' and
+// x' + 256 are P_0 +- w P_1 with w = e^{2 pi i x' / 512}.  The two 256-point transforms
+// of one depth take the place of the two depths in the tiles above (columns (q2, e)
+// and (x1, e)), so a wave owns one depth and all 512 columns, and the lanes c and
+// c ^ 16 that hold P_0(x') and P_1(x') exchange them for the combination.  With
+// q' = 16 q1 + q2, coefficient q = 32 q1 + 2 q2 + e sits in staged row 2 q2 + e.
 //
 // Matrix-core operand layouts (lane l, h = l / 32, c = l % 32):
 //   v_mfma_f32_32x32x2_f32:        A[c][2t + h],  B[2t + h][c],  t = 0..15 (k-steps)
@@ -41,18 +52,21 @@ namespace pam {
 constexpr int kFfN1 = 16;                 // stage-1 radix (and stage-3 radix at N = 256)
 constexpr int kFfRow = 18;                // float2 pitch of a staged / transposed row of 16
 constexpr int kFfZz = 16 * kFfRow + 16;   // float2 pitch of one depth's 16 rows in the transpose buffer
-constexpr int kFfWaves = 8;               // waves per workgroup (2 depths each)
-constexpr int kFfDepths = 2 * kFfWaves;   // depths per workgroup
+constexpr int kFfWaves = 8;               // waves per workgroup (2 / R depths each)
 
-// Staged inputs of one bin: G [NSUB][16 q2][kFfRow] float2 then kz [16 q2][kFfRow] doubles.
-template <int NSUB>
-__host__ __device__ constexpr int ff_stage_f2() { return (NSUB + 1) * 16 * kFfRow; }
-// Transpose buffer of one wave: [NSUB][2 depths][kFfZz] float2.
+// depths per workgroup
+template <int R>
+__host__ __device__ constexpr int ff_depths() { return 2 * kFfWaves / R; }
+// Staged inputs of one bin: G [NSUB][16 R rows][kFfRow] float2 then kz [16 R rows][kFfRow]
+// doubles; row = q2 (R = 1) or 2 q2 + e (R = 2), 16 q1 per row.
+template <int NSUB, int R>
+__host__ __device__ constexpr int ff_stage_f2() { return (NSUB + 1) * 16 * R * kFfRow; }
+// Transpose buffer of one wave: [NSUB][2 depths or halves][kFfZz] float2.
 template <int NSUB>
 __host__ __device__ constexpr int ff_tr_f2() { return NSUB * 2 * kFfZz; }
-template <int NSUB>
+template <int NSUB, int R = 1>
 inline size_t k3ff_lds() {
-  return (size_t)(2 * ff_stage_f2<NSUB>() + kFfWaves * ff_tr_f2<NSUB>()) * sizeof(float2);
+  return (size_t)(2 * ff_stage_f2<NSUB, R>() + kFfWaves * ff_tr_f2<NSUB>()) * sizeof(float2);
 }
 
 // Workgroup index -> (frame, depth tile, bin split).  Consecutive workgroups are
@@ -73,33 +87,43 @@ struct WgFF {
   }
 };
 
-// One 16-byte piece of a bin's staged inputs per thread (512 threads cover NSUB <= 3).
-template <int NSUB>
+// One 16-byte piece of a bin's staged inputs per thread and pass, R passes (512 R
+// pieces cover NSUB <= 3).  K2 writes a bin's coefficients of sub-aperture i in
+// [i][row][q1] order and the kz table is [row][q1], so piece k of thread tid is
+// element 2 (tid + 512 k).  The pieces are separate members (not an array) so that
+// they stay in registers.
+template <int NSUB, int R>
 struct FfPiece {
-  uint4 v;
-  bool on;
-  int dst;   // float2 offset in the stage buffer
-  __device__ FfPiece(int tid) {
-    constexpr int ng = NSUB * 128;                 // pieces of G (2 complex each)
-    on = tid < ng + 128;
-    if (tid < ng) {
-      const int e = 2 * tid, i = e >> 8, q2 = (e >> 4) & 15, q1 = e & 15;
-      dst = (i * 16 + q2) * kFfRow + q1;
-    } else {
-      const int e = 2 * (tid - ng), q2 = e >> 4, q1 = e & 15;
-      dst = NSUB * 16 * kFfRow + q2 * kFfRow + q1;          // doubles at float2 granularity
+  static constexpr int NQ = 256 * R;               // coefficients per sub-aperture
+  static constexpr int NG = NSUB * NQ / 2;         // pieces of G (2 complex each)
+  uint4 v0, v1;
+  int dst0, dst1;   // float2 offsets in the stage buffer, -1 for no piece
+  static __device__ int where(int pi) {
+    if (pi < NG) {
+      const int e = 2 * pi, i = e / NQ, row = (e % NQ) >> 4, q1 = e & 15;
+      return (i * 16 * R + row) * kFfRow + q1;
     }
+    if (pi < NG + NQ / 2) {
+      const int e = 2 * (pi - NG), row = e >> 4, q1 = e & 15;
+      return NSUB * 16 * R * kFfRow + row * kFfRow + q1;       // doubles at float2 granularity
+    }
+    return -1;
+  }
+  static __device__ uint4 fetch(const K3Args& a, int f, int b, int pi) {
+    if (pi < NG) return *reinterpret_cast<const uint4*>(a.coeffs + ((size_t)f * a.n_sel + b) * NSUB * NQ + 2 * pi);
+    return *reinterpret_cast<const uint4*>(a.kz_ff + (size_t)b * NQ + 2 * (pi - NG));
+  }
+  __device__ FfPiece(int tid) {
+    dst0 = where(tid);
+    dst1 = R > 1 ? where(tid + 512) : -1;
   }
   __device__ __forceinline__ void load(const K3Args& a, int f, int b, int tid) {
-    constexpr int ng = NSUB * 128;
-    if (!on) return;
-    if (tid < ng)
-      v = *reinterpret_cast<const uint4*>(a.coeffs + ((size_t)f * a.n_sel + b) * NSUB * 256 + 2 * tid);
-    else
-      v = *reinterpret_cast<const uint4*>(a.kz_ff + (size_t)b * 256 + 2 * (tid - ng));
+    if (dst0 >= 0) v0 = fetch(a, f, b, tid);
+    if (R > 1 && dst1 >= 0) v1 = fetch(a, f, b, tid + 512);
   }
   __device__ __forceinline__ void store(float2* stage) const {
-    if (on) *reinterpret_cast<uint4*>(stage + dst) = v;
+    if (dst0 >= 0) *reinterpret_cast<uint4*>(stage + dst0) = v0;
+    if (R > 1 && dst1 >= 0) *reinterpret_cast<uint4*>(stage + dst1) = v1;
   }
 };
 
@@ -117,20 +141,36 @@ struct FfTw {
   }
 };
 
-// Lane (c, h) of a wave holds depth d0 + c/16 and columns x = c%16 + 16 x2,
-// x2 = 8(v/4) + 4h + v%4 for v = 0..7.
-template <int NSUB, bool COH = false>
+// Combination twiddles e^{2 pi i x' / 512} of this lane's 8 stage-3 outputs (N = 512).
+struct FfTw2 {
+  float2 t[8];
+  __device__ FfTw2() {}
+  __device__ FfTw2(const K3Args& a, int lane) {
+    const float4* src = reinterpret_cast<const float4*>(a.ff_tw2) + lane * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 q = src[k];
+      t[2 * k] = make_float2(q.x, q.y);
+      t[2 * k + 1] = make_float2(q.z, q.w);
+    }
+  }
+};
+
+// Lane (c, h) of a wave holds columns x = c%16 + 16 x2 (+ 256 for c >= 16 at N = 512),
+// x2 = 8(v/4) + 4h + v%4 for v = 0..7, of depth d0 + c/16 (N = 256) or d0 (N = 512).
+template <int NSUB, bool COH = false, int R = 1>
 __device__ __forceinline__ void ff_store(const K3Args& a, int sp, int f, int d0, int lane,
                                          const float (&accS)[NSUB][8],
                                          const float (&accC)[AccCount<NSUB>::pairs > 0 ? AccCount<NSUB>::pairs : 1][8],
                                          const float (*accG)[8] = nullptr) {
   constexpr int NA = COH ? 5 : AccCount<NSUB>::total;
   constexpr int NP = AccCount<NSUB>::pairs;
+  constexpr int N = 256 * R;
   const int c = lane & 31, h = lane >> 5;
-  const int row = d0 + (c >> 4);
+  const int row = R == 1 ? d0 + (c >> 4) : d0;
   if (row >= a.n_z) return;
-  const size_t plane = (size_t)a.n_z * 256;
-  float* dst = a.accum + ((size_t)sp * a.F + f) * NA * plane + (size_t)row * 256 + (c & 15);
+  const size_t plane = (size_t)a.n_z * N;
+  float* dst = a.accum + ((size_t)sp * a.F + f) * NA * plane + (size_t)row * N + (c & 15) + (R == 1 ? 0 : 256 * (c >> 4));
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     const int x = 16 * (8 * (v >> 2) + 4 * h + (v & 3));
@@ -188,25 +228,30 @@ struct FfOps {
 // COH (n_sub = 1 only): the back half also accumulates, per pixel, the cross-spectra
 // with its lateral pair partner (column x ^ 1, the adjacent lane) and its axial pair
 // partner (depth 2i <-> 2i + 1, the lane 16 away), G = sum over bins of p conj(p').
-template <typename T, int PASSES, int NSUB, bool COH = false>
+template <typename T, int PASSES, int NSUB, bool COH = false, int R = 1>
 __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
-  static_assert(!COH || NSUB == 1, "pair cross-spectra come with the full-aperture sums only");
+  static_assert(!COH || (NSUB == 1 && R == 1), "pair cross-spectra come with the full-aperture sums at N = 256");
+  static_assert(R == 1 || R == 2, "N = 256 or 512");
   constexpr bool F32 = std::is_same<T, float>::value;
   constexpr bool SCALED = std::is_same<T, _Float16>::value;   // keep K2's scale through stage 3
   constexpr int NP = AccCount<NSUB>::pairs;
   typedef typename std::conditional<F32, float, typename Mma<typename std::conditional<F32, __bf16, T>::type>::v8>::type v8;
   extern __shared__ float2 lds2[];
-  float2* stage = lds2;                                          // [2][ff_stage_f2]
+  float2* stage = lds2;                                          // [2][ff_stage_f2<NSUB, R>]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  float2* tr = lds2 + 2 * ff_stage_f2<NSUB>() + w * ff_tr_f2<NSUB>();
+  float2* tr = lds2 + 2 * ff_stage_f2<NSUB, R>() + w * ff_tr_f2<NSUB>();
   const WgFF wg(a);
   const int f = wg.f;
   const int c = lane & 31, h = lane >> 5;
-  const int q2 = c & 15, zz = c >> 4;                            // stage-1 column; (x1, zz) of stage 3
-  const int d0 = wg.dt * kFfDepths + 2 * w;
+  // stage-1 column (q2, zz), stage-3 column (x1, zz): zz is the depth (N = 256) or the
+  // parity e of q (N = 512)
+  const int q2 = c & 15, zz = c >> 4;
+  const int d0 = R == 1 ? wg.dt * ff_depths<R>() + 2 * w : wg.dt * ff_depths<R>() + w;
+  const int depth = R == 1 ? d0 + zz : d0;
+  const int srow = R == 1 ? q2 : 2 * q2 + zz;                    // staged row of this lane's inputs
   // rows beyond the grid run with z = 0: their pixels stay in their own columns of
   // both stages and are never stored
-  const double z = d0 + zz < a.n_z ? a.z[d0 + zz] : 0.0;
+  const double z = depth < a.n_z ? a.z[depth] : 0.0;
   const bool lag = w >= 4;
 
   // constant 16-point DFT operands
@@ -231,6 +276,8 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
     }
   }
   const FfTw tw(a, lane);
+  FfTw2 tw2;
+  if constexpr (R == 2) tw2 = FfTw2(a, lane);
   float accS[NSUB][8];
   float accC[NP > 0 ? NP : 1][8];
   float accG[COH ? 4 : 1][8];      // Re, Im of the lateral, then of the axial pair sums
@@ -286,8 +333,8 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
 
   // front half of bin b: stage-1 operands from the staged inputs, products, twiddle, transpose
   auto front = [&](int b) {
-    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB>();
-    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * kFfRow) + q2 * kFfRow + 8 * h;
+    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB, R>();
+    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * R * kFfRow) + srow * kFfRow + 8 * h;
     // propagator at the lane's 8 wavenumbers (Eq. 2): phase in FP64 reduced to
     // [-1/2, 1/2] cycle, hardware sin/cos; evanescent values (kz < 0 in the table) are
     // replaced in one branch taken only by lanes that hold any
@@ -307,7 +354,7 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
     v8 bh[NSUB][2], bl[NSUB][2];
 #pragma unroll
     for (int i = 0; i < NSUB; ++i) {
-      const float4* g = reinterpret_cast<const float4*>(st + (i * 16 + q2) * kFfRow + 8 * h);
+      const float4* g = reinterpret_cast<const float4*>(st + (i * 16 * R + srow) * kFfRow + 8 * h);
       float x[16];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -361,6 +408,15 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
       for (int i = 0; i < NSUB; ++i) {
         pr[i] = SCALED ? C[i][v] * inv : C[i][v];
         pim[i] = SCALED ? C[i][v + 8] * inv : C[i][v + 8];
+        if constexpr (R == 2) {
+          // P_0 +- w P_1: lane half zz = 0 holds P_0(x'), zz = 1 P_1(x'), x' its column
+          const float or_ = __shfl_xor(pr[i], 16), oi = __shfl_xor(pim[i], 16);
+          const float2 p0 = zz ? make_float2(or_, oi) : make_float2(pr[i], pim[i]);
+          const float2 p1 = zz ? make_float2(pr[i], pim[i]) : make_float2(or_, oi);
+          const float2 t = cmul(tw2.t[v], p1);
+          pr[i] = zz ? p0.x - t.x : p0.x + t.x;
+          pim[i] = zz ? p0.y - t.y : p0.y + t.y;
+        }
         accS[i][v] = fmaf(pr[i], pr[i], fmaf(pim[i], pim[i], accS[i][v]));
       }
       if constexpr (NSUB == 3) {
@@ -382,7 +438,7 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
     }
   };
 
-  FfPiece<NSUB> pc(tid);
+  FfPiece<NSUB, R> pc(tid);
   if (wg.b_begin < wg.b_end) {
     pc.load(a, f, wg.b_begin, tid);
     pc.store(stage);
@@ -395,10 +451,10 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
     if (lag && b > wg.b_begin) back(b - 1);
     if (has) front(b);
     if (!lag && has) back(b);
-    if (more) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB>());
+    if (more) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB, R>());
     __syncthreads();
   }
-  ff_store<NSUB, COH>(a, wg.sp, f, d0, lane, accS, accC, accG);
+  ff_store<NSUB, COH, R>(a, wg.sp, f, d0, lane, accS, accC, accG);
 }
 
 }  // namespace pam

@@ -314,11 +314,12 @@ struct K3Args {
   float* accum;            // [n_split][F][n_acc][n_z][N]
   int32_t N, n_z, n_sel, F, n_dt, n_xg, n_split, bins_per_split, zero_evanescent;
   // factored-transform kernels (k3_factored.hpp)
-  const double* kz_ff;     // [n_sel][N2][N1] signed kz / (2 pi) at q = N2 q1 + q2
+  const double* kz_ff;     // [n_sel][N / 16][16] signed kz / (2 pi) at q = (N / 16) q1 + r, stored at [r][q1]
   const float* ff_w32;     // [64 lanes][16] 16-point DFT matrix, FP32 operand order
   const void* ff_w16;      // [64 lanes][2 k-steps][hi 8, lo 8] 16-point DFT matrix, 16-bit operand order
   const float2* ff_tw;     // [64 lanes][8] twiddles e^{2 pi i q2 x1 / N} of the lane's stage-1 outputs (/ 16 for FP16)
   const int32_t* ev_bin;   // [n_sel] 1 if the bin has evanescent lateral wavenumbers
+  const float2* ff_tw2;    // [64 lanes][8] e^{2 pi i x' / 512} of the lane's stage-3 outputs (N = 512)
 };
 
 template <int NSUB>

@@ -106,10 +106,11 @@ struct pam_plan_s {
   float* d_basis_lane = nullptr;  // [N/32][N][2][16]: the basis in matrix-core operand order
   uint16_t* d_bhi = nullptr;   // [N/8][N][8] basis (slot groups, x, slots), 16-bit hi (split kernels)
   uint16_t* d_blo = nullptr;   // same layout, 16-bit lo
-  bool ff = false;             // inverse lateral transform factored into two 16-point stages (N = 256)
+  bool ff = false;             // inverse lateral transform factored into two 16-point stages (N = 256, 512)
   float* d_ff_w32 = nullptr;   // [64][16] 16-point DFT matrix in FP32 operand order
   uint16_t* d_ff_w16 = nullptr;  // [64][2][16] the same in 16-bit operand order, hi then lo per k-step
   float2* d_ff_tw = nullptr;   // [64][8] twiddles / 16 in stage-1 output order
+  float2* d_ff_tw2 = nullptr;  // [64][8] N = 512 combination twiddles in stage-3 output order
   // frequency-domain delay-and-sum (pam_fd_tea_tax)
   double fs = 0, c = 0;        // sampling rate, sound speed
   double dx = 0, x_first = 0;  // lateral grid spacing and coordinate of column 0
@@ -201,7 +202,8 @@ LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
     // 16 depths x all 256 columns per workgroup, 8 waves of 2 depths
     s.fw = -1;
     s.nw = pam::kFfWaves;
-    s.n_dt = (p->n_z + pam::kFfDepths - 1) / pam::kFfDepths;
+    const int dpw = p->N == 512 ? pam::ff_depths<2>() : pam::ff_depths<1>();
+    s.n_dt = (p->n_z + dpw - 1) / dpw;
     s.n_xg = 1;
   } else if (p->N == 256 || p->N == 512) {
     // 32 depths x 256 columns per workgroup, 8 waves each generating and multiplying
@@ -354,17 +356,22 @@ hipError_t launch_precx(int precision, const pam::K3Args& a, int blocks, hipStre
   }
 }
 
+template <int NSUB, int R>
+hipError_t launch_ff_r(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+  using namespace pam;
+  const size_t lds = k3ff_lds<NSUB, R>();
+  switch (precision) {
+    case PAM_PREC_SPLIT_BF16: return launch_fused(k3ff<__bf16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_SPLIT_FP16: return launch_fused(k3ff<_Float16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_BF16: return launch_fused(k3ff<__bf16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_FP16: return launch_fused(k3ff<_Float16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    default: return launch_fused(k3ff<float, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+  }
+}
+
 template <int NSUB>
 hipError_t launch_ff(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
-  using namespace pam;
-  const size_t lds = k3ff_lds<NSUB>();
-  switch (precision) {
-    case PAM_PREC_SPLIT_BF16: return launch_fused(k3ff<__bf16, 3, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_SPLIT_FP16: return launch_fused(k3ff<_Float16, 3, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_BF16: return launch_fused(k3ff<__bf16, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_FP16: return launch_fused(k3ff<_Float16, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-    default: return launch_fused(k3ff<float, 1, NSUB>, kFfWaves, lds, lds, a, blocks, st);
-  }
+  return a.N == 512 ? launch_ff_r<NSUB, 2>(precision, a, blocks, st) : launch_ff_r<NSUB, 1>(precision, a, blocks, st);
 }
 
 template <int NSUB>
@@ -536,13 +543,14 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       }
   }
 
-  // Factored transform (N = 256 = 16 x 16): the 16-point DFT matrix W(x, m) = e^{2 pi i m x / 16}
-  // in real form, rows (x, re/im) = x + 16 ro, and the stage twiddles, all in lane order of
-  // the matrix-core operands.  Lane l: column c = l % 32, half h = l / 32.
-  p->ff = (N == 256);
+  // Factored transform (N = 256 = 16 x 16; N = 512 as two such transforms over even and
+  // odd q): the 16-point DFT matrix W(x, m) = e^{2 pi i m x / 16} in real form, rows
+  // (x, re/im) = x + 16 ro, the stage twiddles and (N = 512) the combination twiddles, all
+  // in lane order of the matrix-core operands.  Lane l: column c = l % 32, half h = l / 32.
+  p->ff = (N == 256 || N == 512);
   std::vector<float> ff_w32;
   std::vector<uint16_t> ff_w16;
-  std::vector<float2> ff_tw;
+  std::vector<float2> ff_tw, ff_tw2;
   if (p->ff) {
     auto wval = [](int row, int m, int ri) {
       const int x = row % 16, ro = row / 16;
@@ -575,6 +583,15 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
         ff_tw[l * 8 + v] = make_float2((float)(std::cos(th) * sc), (float)(std::sin(th) * sc));
       }
     }
+    // stage-3 output v of lane l is x' = c % 16 + 16 (8(v/4) + 4h + v%4) of half c / 16
+    ff_tw2.assign(64 * 8, make_float2(0.f, 0.f));
+    if (N == 512)
+      for (int l = 0; l < 64; ++l)
+        for (int v = 0; v < 8; ++v) {
+          const int c = l % 32, h = l / 32, xp = c % 16 + 16 * (8 * (v / 4) + 4 * h + v % 4);
+          const double th = 2.0 * kPi * (double)xp / 512.0;
+          ff_tw2[l * 8 + v] = make_float2((float)std::cos(th), (float)std::sin(th));
+        }
   }
 
   do {
@@ -586,6 +603,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       if ((st = upload(p, &p->d_ff_w32, ff_w32.data(), ff_w32.size())) != PAM_OK) break;
       if ((st = upload(p, &p->d_ff_w16, ff_w16.data(), ff_w16.size())) != PAM_OK) break;
       if ((st = upload(p, &p->d_ff_tw, ff_tw.data(), ff_tw.size())) != PAM_OK) break;
+      if ((st = upload(p, &p->d_ff_tw2, ff_tw2.data(), ff_tw2.size())) != PAM_OK) break;
     }
     if ((st = upload(p, &p->d_z, z.data(), z.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_tw, tw.data(), tw.size())) != PAM_OK) break;
@@ -617,13 +635,14 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       if ((st = upload(p, &lv.d_ksel, ksel.data(), ksel.size())) != PAM_OK) break;
       if ((st = upload(p, &lv.d_kz, kz_lv.data(), kz_lv.size())) != PAM_OK) break;
       if (p->ff) {
-        // [n_sel][q2][q1] at q = 16 q1 + q2; kz depends on q through min(q, N - q)
+        // [n_sel][r][q1] at q = (N / 16) q1 + r; kz depends on q through min(q, N - q)
         std::vector<double> kzff((size_t)lv.n_sel * N);
+        const int n2 = N / 16;
         for (int b = 0; b < lv.n_sel; ++b)
-          for (int q2 = 0; q2 < 16; ++q2)
+          for (int r = 0; r < n2; ++r)
             for (int q1 = 0; q1 < 16; ++q1) {
-              const int q = 16 * q1 + q2, qf = std::min(q, N - q);
-              kzff[(size_t)b * N + q2 * 16 + q1] = kz_lv[(size_t)b * pam::kz_row(N) + qf];
+              const int q = n2 * q1 + r, qf = std::min(q, N - q);
+              kzff[(size_t)b * N + r * 16 + q1] = kz_lv[(size_t)b * pam::kz_row(N) + qf];
             }
         if ((st = upload(p, &lv.d_kzff, kzff.data(), kzff.size())) != PAM_OK) break;
         std::vector<int32_t> ev(lv.n_sel, 0);
@@ -762,7 +781,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
     const LaunchShape s = k3_shape(p, F, lv->n_sel);
     pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, p->d_basis_lane, accum,
                   p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent,
-                  lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw, lv->d_ev};
+                  lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw, lv->d_ev, p->d_ff_tw2};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
     if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
     if (launch_k3(p->precision, p->n_sub, s, a, (int)blocks, stream, p->coherence) != hipSuccess || !mark(3))

@@ -241,10 +241,11 @@ def test_workspace_too_small_is_rejected(pam, torch_cuda):
 
 
 # ------------------------------------------------------------------ lateral grid sizes
-# The fields kernel has three tilings selected by the lateral size N: 32 depths x 256
-# columns with fused wave roles (N = 256, 512), 16 depths x 64 CT columns (other
-# multiples of 64), 32 depths x 32 NW columns (the remaining multiples of 32).  Each
-# grid below reaches one of them with a ragged depth tail; the split form runs too.
+# The fields kernel has three tilings selected by the lateral size N: the factored
+# two-stage transform (N = 256: 16 depths per workgroup; N = 512: 8 depths, even and odd
+# wavenumbers combined), 16 depths x 64 CT columns (other multiples of 64), 32 depths x
+# 32 NW columns (the remaining multiples of 32).  Each grid below reaches one of them
+# with a ragged depth tail; the split form runs too.
 SPLIT_TOL = (1e-3, 1e-3)
 
 
@@ -414,3 +415,19 @@ def test_coherence_needs_one_subaperture(pam, torch_cuda):
     g = g.replace(depths_m=g.depths_m[:37], n_sub=1, apod=np.ones((1, g.n_elements), np.uint8), coherence=1)
     with pytest.raises(pam.PamError):
         pam.pam_plan(g, 0, "fp32")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16", "split_fp16", "bf16"])
+@pytest.mark.parametrize("n_sub", [1, 2, 3])
+def test_factored_512_forms(pam, torch_cuda, precision, n_sub):
+    """N = 512 on the factored kernel (two 256-point transforms over even and odd
+    wavenumbers, combined per pixel pair x, x + 256) in every sub-aperture count and operand
+    form: 13 depths (one full 8-depth tile and a ragged one), two frames."""
+    g, rf0 = _grid_case(64, 512, 13, seed=5120)
+    g = g.replace(n_sub=n_sub)
+    _, rf1 = _grid_case(64, 512, 13, seed=5121)
+    rf = np.stack([rf0, rf1])
+    res = run(pam, torch_cuda, g, rf, precision=precision, want_pairs=n_sub > 1)
+    tol_i, tol_rho = {"fp32": (TOL_I, TOL_RHO), "bf16": (1e-2, 5e-2)}.get(precision, SPLIT_TOL)
+    for f in range(2):
+        check_end_to_end(res, O.as_tax(rf[f], g), f, tol_i=tol_i, tol_rho=tol_rho)
