@@ -13,7 +13,7 @@
  *   Activations: BF16, NHWC ([batch][h][w][channels], channels fastest) with a
  *   channel stride ld >= channels, so a tensor may be a channel slice of a wider
  *   buffer (concatenation without copies).  Channel counts used by the 3x3
- *   kernels are multiples of 16 (inputs) and 32 (outputs); w is a multiple of 32.
+ *   kernels are multiples of 32; w is a multiple of 32.
  *   Master weights: FP32 [9][c_in][c_out], tap t = 3 (dh + 1) + (dw + 1); the
  *   convolution is a cross-correlation with zero padding.  Matrix-core products
  *   take BF16 operands and accumulate in FP32.
@@ -112,7 +112,8 @@ pam_status_t pam_nn_features(const float* energy, int32_t batch, int64_t pixels,
 /* Network input from the accumulator channels of a full-aperture plan built with
  * coherence = 1 (pam.h): accum FP32 [n_split][batch][5][n_z][n_x] (S, Re G_x, Im G_x,
  * Re G_z, Im G_z), consecutive splits split_stride floats apart (ignored when n_split = 1).
- * Writes energy FP32 [batch][n_z][n_x] = S summed over the splits and BF16
+ * Writes energy FP32 [batch][n_z][n_x] = S summed over the splits, frame_max FP32 [batch]
+ * = its maximum over each frame (caller-owned, overwritten) and BF16
  * [batch][n_z * n_x][32] features:
  *   0: clamp(log10(S / max S) / 6 + 1, 0, 1)        1: S / max S
  *   2-4: |c_x|, Re c_x, Im c_x with c_x = G_x / sqrt(S(z, x0) S(z, x0 + 1)) of the
@@ -121,7 +122,8 @@ pam_status_t pam_nn_features(const float* energy, int32_t batch, int64_t pixels,
  *   8-31: 0
  * A pair whose energies multiply to 0 has c = 0.  n_z and n_x must be even. */
 pam_status_t pam_nn_coherence_features(const float* accum, int32_t n_split, int64_t split_stride, int32_t batch,
-                                       int32_t n_z, int32_t n_x, void* out, float* energy, void* hip_stream);
+                                       int32_t n_z, int32_t n_x, void* out, float* energy, float* frame_max,
+                                       void* hip_stream);
 
 /* Predicted relative L2 error of each frame's image mask^2 E when the mask is off by
  * err per pixel: est[f] = ||2 mask err E|| / ||mask^2 E|| over the frame's pixels (FP64

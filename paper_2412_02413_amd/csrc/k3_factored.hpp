@@ -45,7 +45,7 @@
 #pragma once
 #include <type_traits>
 
-#include "k3_fields_fused.hpp"
+#include "k3_fields16.hpp"
 
 namespace pam {
 

@@ -310,7 +310,6 @@ struct K3Args {
   const float* basis;      // [N][N] slot-major fixed real basis (FP32 kernel)
   const void* basis_hi;    // [N/8 slot groups][N x][8 slots] basis, 16-bit hi part (split kernels)
   const void* basis_lo;    // same layout, 16-bit lo part
-  const float* basis_lane; // [N/32 chunks][N x][2][16] basis in 32x32x2 operand order (fused FP32 kernel)
   float* accum;            // [n_split][F][n_acc][n_z][N]
   int32_t N, n_z, n_sel, F, n_dt, n_xg, n_split, bins_per_split, zero_evanescent;
   // factored-transform kernels (k3_factored.hpp)

@@ -14,7 +14,6 @@
 #include "kernels.hpp"
 #include "k3_fields.hpp"
 #include "k3_fields16.hpp"
-#include "k3_fields_fused.hpp"
 #include "k3_factored.hpp"
 #include "k3_tea.hpp"
 
@@ -103,7 +102,6 @@ struct pam_plan_s {
   float* d_masks = nullptr;    // [n_sub][L]
   int32_t col0 = 0, col_step = 1;  // grid column of element l: col0 + col_step * l
   float* d_basis = nullptr;    // [N][N] slot-major cos/sin basis (FP32 kernel)
-  float* d_basis_lane = nullptr;  // [N/32][N][2][16]: the basis in matrix-core operand order
   uint16_t* d_bhi = nullptr;   // [N/8][N][8] basis (slot groups, x, slots), 16-bit hi (split kernels)
   uint16_t* d_blo = nullptr;   // same layout, 16-bit lo
   bool ff = false;             // inverse lateral transform factored into two 16-point stages (N = 256, 512)
@@ -190,7 +188,7 @@ std::vector<int32_t> select_bins(const pam_geometry_t* g) {
 struct LaunchShape {
   int n_dt, nw, xt, n_xg, n_split, bins_per_split;
   int ct;   // > 0: 16-depth kernels with ct 16-column tiles per consumer wave
-  int fw;   // > 0: fused-role kernels with fw waves (32 depths x 32 fw columns)
+  int fw;   // < 0: the factored two-stage kernel (N = 256, 512)
 };
 
 LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
@@ -205,12 +203,6 @@ LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
     const int dpw = p->N == 512 ? pam::ff_depths<2>() : pam::ff_depths<1>();
     s.n_dt = (p->n_z + dpw - 1) / dpw;
     s.n_xg = 1;
-  } else if (p->N == 256 || p->N == 512) {
-    // 32 depths x 256 columns per workgroup, 8 waves each generating and multiplying
-    s.fw = 8;
-    s.nw = s.fw;
-    s.n_dt = (p->n_z + 31) / 32;
-    s.n_xg = p->N / 256;
   } else if (p->N % 64 == 0) {
     // 16 depths x 64 ct columns per workgroup (4 consumer + 4 producer waves)
     s.ct = p->N % 256 == 0 ? 4 : (p->N % 128 == 0 ? 2 : 1);
@@ -316,10 +308,10 @@ hipError_t launch_prec16(int precision, const pam::K3Args& a, int blocks, hipStr
   }
 }
 
-// Fused-role kernels: the LDS size depends on N (staged bin inputs); the kernel
-// attribute is set once for the largest N an instantiation serves.
+// Kernels with more than 64 KB of dynamic LDS: the attribute is set before each launch
+// for the largest size the instantiation takes.
 template <typename K>
-hipError_t launch_fused(K kernel, int nw, size_t lds, size_t lds_max, const pam::K3Args& a, int blocks,
+hipError_t launch_big_lds(K kernel, int nw, size_t lds, size_t lds_max, const pam::K3Args& a, int blocks,
                         hipStream_t st) {
   const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
@@ -329,43 +321,16 @@ hipError_t launch_fused(K kernel, int nw, size_t lds, size_t lds_max, const pam:
   return hipGetLastError();
 }
 
-// slots per stage of the fused-role kernels
-constexpr int kFusedKC = 64;
-
-template <int NSUB, int NPC>
-hipError_t launch_precx(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
-  using namespace pam;
-  constexpr int KC = kFusedKC;
-  const int N = a.N, NM = 256 * NPC;   // largest N served by this instantiation
-  switch (precision) {
-    case PAM_PREC_SPLIT_BF16:
-      return launch_fused(k3x_split<__bf16, 3, NSUB, NPC, KC>, 8, k3x_split_lds<3, NSUB, KC>(N),
-                          k3x_split_lds<3, NSUB, KC>(NM), a, blocks, st);
-    case PAM_PREC_SPLIT_FP16:
-      return launch_fused(k3x_split<_Float16, 3, NSUB, NPC, KC>, 8, k3x_split_lds<3, NSUB, KC>(N),
-                          k3x_split_lds<3, NSUB, KC>(NM), a, blocks, st);
-    case PAM_PREC_BF16:
-      return launch_fused(k3x_split<__bf16, 1, NSUB, NPC, KC>, 8, k3x_split_lds<1, NSUB, KC>(N),
-                          k3x_split_lds<1, NSUB, KC>(NM), a, blocks, st);
-    case PAM_PREC_FP16:
-      return launch_fused(k3x_split<_Float16, 1, NSUB, NPC, KC>, 8, k3x_split_lds<1, NSUB, KC>(N),
-                          k3x_split_lds<1, NSUB, KC>(NM), a, blocks, st);
-    default:
-      return launch_fused(k3x_fp32<NSUB, NPC, KC>, 8, k3x_fp32_lds<NSUB, KC>(N), k3x_fp32_lds<NSUB, KC>(NM), a,
-                          blocks, st);
-  }
-}
-
 template <int NSUB, int R>
 hipError_t launch_ff_r(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
   using namespace pam;
   const size_t lds = k3ff_lds<NSUB, R>();
   switch (precision) {
-    case PAM_PREC_SPLIT_BF16: return launch_fused(k3ff<__bf16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_SPLIT_FP16: return launch_fused(k3ff<_Float16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_BF16: return launch_fused(k3ff<__bf16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_FP16: return launch_fused(k3ff<_Float16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
-    default: return launch_fused(k3ff<float, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_SPLIT_BF16: return launch_big_lds(k3ff<__bf16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_SPLIT_FP16: return launch_big_lds(k3ff<_Float16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_BF16: return launch_big_lds(k3ff<__bf16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_FP16: return launch_big_lds(k3ff<_Float16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    default: return launch_big_lds(k3ff<float, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
   }
 }
 
@@ -377,8 +342,6 @@ hipError_t launch_ff(int precision, const pam::K3Args& a, int blocks, hipStream_
 template <int NSUB>
 hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
   if (s.fw < 0) return launch_ff<NSUB>(precision, a, blocks, st);
-  if (s.fw == 8) return a.N > 256 ? launch_precx<NSUB, 2>(precision, a, blocks, st)
-                                   : launch_precx<NSUB, 1>(precision, a, blocks, st);
   if (s.ct == 4) return launch_prec16<NSUB, 4>(precision, a, blocks, st);
   if (s.ct == 2) return launch_prec16<NSUB, 2>(precision, a, blocks, st);
   if (s.ct == 1) return launch_prec16<NSUB, 1>(precision, a, blocks, st);
@@ -393,11 +356,11 @@ hipError_t launch_k3(int precision, int n_sub, const LaunchShape& s, const pam::
     using namespace pam;
     const size_t lds = k3ff_lds<1>();
     switch (precision) {
-      case PAM_PREC_SPLIT_BF16: return launch_fused(k3ff<__bf16, 3, 1, true>, kFfWaves, lds, lds, a, blocks, st);
-      case PAM_PREC_SPLIT_FP16: return launch_fused(k3ff<_Float16, 3, 1, true>, kFfWaves, lds, lds, a, blocks, st);
-      case PAM_PREC_BF16: return launch_fused(k3ff<__bf16, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
-      case PAM_PREC_FP16: return launch_fused(k3ff<_Float16, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
-      default: return launch_fused(k3ff<float, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      case PAM_PREC_SPLIT_BF16: return launch_big_lds(k3ff<__bf16, 3, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      case PAM_PREC_SPLIT_FP16: return launch_big_lds(k3ff<_Float16, 3, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      case PAM_PREC_BF16: return launch_big_lds(k3ff<__bf16, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      case PAM_PREC_FP16: return launch_big_lds(k3ff<_Float16, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
+      default: return launch_big_lds(k3ff<float, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
     }
   }
   switch (n_sub) {
@@ -502,8 +465,11 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     const double a = 2.0 * kPi * (double)i / (double)N;
     twx[i] = make_float2((float)std::cos(a), (float)-std::sin(a));
   }
-  std::vector<float> basis((size_t)N * N);
-  for (int s = 0; s < N; ++s) {
+  // Factored transform for N = 256 and 512 (k3_factored.hpp); the other lateral sizes
+  // take the folded DFT basis (k3_fields*.hpp), built only for them.
+  p->ff = (N == 256 || N == 512);
+  std::vector<float> basis(p->ff ? 0 : (size_t)N * N);
+  for (int s = 0; s < (p->ff ? 0 : N); ++s) {
     const int q = s >> 1;
     for (int x = 0; x < N; ++x) {
       double v;
@@ -518,16 +484,8 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     }
   }
 
-  // operand order of the fused FP32 kernel: slot 32 c + 2 j + h of column x at ((c N + x) 2 + h) 16 + j
-  std::vector<float> basis_lane((size_t)N * N);
-  for (int s = 0; s < N; ++s)
-    for (int x = 0; x < N; ++x) {
-      const int c = s / 32, sl = s % 32;
-      basis_lane[(((size_t)c * N + x) * 2 + (sl & 1)) * 16 + (sl >> 1)] = basis[(size_t)s * N + x];
-    }
-
   std::vector<uint16_t> bhi, blo;
-  if (is_split(p->precision)) {
+  if (is_split(p->precision) && !p->ff) {
     bhi.resize((size_t)N * N);
     blo.resize((size_t)N * N);
     const bool h16 = is_fp16(p->precision);
@@ -547,7 +505,6 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
   // odd q): the 16-point DFT matrix W(x, m) = e^{2 pi i m x / 16} in real form, rows
   // (x, re/im) = x + 16 ro, the stage twiddles and (N = 512) the combination twiddles, all
   // in lane order of the matrix-core operands.  Lane l: column c = l % 32, half h = l / 32.
-  p->ff = (N == 256 || N == 512);
   std::vector<float> ff_w32;
   std::vector<uint16_t> ff_w16;
   std::vector<float2> ff_tw, ff_tw2;
@@ -595,7 +552,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
   }
 
   do {
-    if (is_split(p->precision)) {
+    if (is_split(p->precision) && !p->ff) {
       if ((st = upload(p, &p->d_bhi, bhi.data(), bhi.size())) != PAM_OK) break;
       if ((st = upload(p, &p->d_blo, blo.data(), blo.size())) != PAM_OK) break;
     }
@@ -616,8 +573,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
           if (masks[(size_t)i * L + l] != 0.f) subs[l] |= 1 << i;
       if ((st = upload(p, &p->d_subs, subs.data(), subs.size())) != PAM_OK) break;
     }
-    if ((st = upload(p, &p->d_basis, basis.data(), basis.size())) != PAM_OK) break;
-    if ((st = upload(p, &p->d_basis_lane, basis_lane.data(), basis_lane.size())) != PAM_OK) break;
+    if (!p->ff && (st = upload(p, &p->d_basis, basis.data(), basis.size())) != PAM_OK) break;
     // bin subsets for records of n_t / 2^j samples
     for (int stride = 1; p->n_t / stride >= kMinSamples; stride <<= 1) {
       Level lv;
@@ -779,7 +735,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   // K3: fused propagate / inverse lateral transform / cross-spectra
   if (method == 0) {
     const LaunchShape s = k3_shape(p, F, lv->n_sel);
-    pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, p->d_basis_lane, accum,
+    pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, accum,
                   p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent,
                   lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw, lv->d_ev, p->d_ff_tw2};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;

@@ -2,6 +2,7 @@
 // FP32 master weights and accumulation.  See include/pam_nn.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "../../include/pam_nn.h"
@@ -16,80 +17,174 @@ inline bool ok_stream(hipError_t e) { return e == hipSuccess; }
 inline pam_status_t launched() { return hipGetLastError() == hipSuccess ? PAM_OK : PAM_ERR_DEVICE; }
 
 // ---------------------------------------------------------------------------
-// 3x3 convolution as an implicit GEMM on v_mfma_f32_32x32x16_bf16.
+// 3x3 convolution as an implicit GEMM on v_mfma_f32_32x32x16_bf16, staged in LDS.
 // GEMM: rows = 32 consecutive pixels of one image row, columns = 32 output
-// channels, K = 9 taps x k_in channels.  Each lane gathers the 8 channels of
-// its pixel (shifted by the tap, zero outside the image) straight from the
-// NHWC tensor (16 contiguous bytes) and 8 weights of its output channel from
-// the [n_out][9][k_in] layout (16 contiguous bytes).  One wave per 32 pixels x
-// 32 NT output channels (each input fragment feeds NT products), four waves
-// (four pixel tiles) per workgroup.
+// channels, K = 9 taps x k_in channels.  A tile is 4 RW image rows x 32 columns x
+// 32 NO output channels; wave w owns its rows RW w .. RW w + RW - 1, i.e. RW x NO
+// accumulator tiles of 32 x 32.  Per chunk of 32 input channels the workgroup stages
+// in LDS
+//   the input patch: (4 RW + 2) rows x 34 columns (one-pixel halo, zeros outside the
+//     image) x 32 channels, and
+//   the weights: 9 taps x 32 NO output channels x 32 channels,
+// each pixel / output channel padded to 40 BF16 (80 bytes) so that the 32 lanes of a
+// 16-byte operand read spread over the banks.  All 9 taps then read their A operand
+// (pixel shifted by the tap) and B operand from LDS: one A fragment feeds NO
+// products and one B fragment RW products.
+//
+// A workgroup walks a run of tiles (same output-channel group), chunk by chunk.
+// While the products of one (tile, chunk) item run, each thread's pieces of the next
+// item (16 bytes each) are already loading into registers; they go to LDS between
+// the two barriers that close the item.  With a single chunk the weights stay in LDS
+// for the whole run.
 // ---------------------------------------------------------------------------
 struct ConvArgs {
   const bf16* x;
   const bf16* wt;
   const float* bias;
   bf16* y;
-  int64_t P;
-  int32_t ldx, h, w, k_in, ldy, n_out, relu, flip, acc;
+  int32_t ldx, batch, h, w, k_in, ldy, n_out, relu, flip, acc;
+  int32_t n_rt, n_ct;   // row tiles (4 RW rows) and column tiles (32) per image
+  int32_t n_tiles;      // batch n_rt n_ct
+  int32_t run;          // tiles per workgroup
 };
 
-template <int NT>
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t p0 = tile * 32;
-  if (p0 >= a.P) return;  // wave-uniform; the kernel has no barriers
-  const int co0 = blockIdx.y * 32 * NT;
+constexpr int kConvPad = 40;   // BF16 per staged pixel or output channel (32 used)
+
+template <int RW, int NO>
+constexpr int conv_lds_bytes() {
+  return ((4 * RW + 2) * 34 + 9 * 32 * NO) * kConvPad * 2;
+}
+
+template <int RW, int NO>
+__global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a) {
+  constexpr int PR = 4 * RW + 2;                 // patch rows
+  constexpr int CO = 32 * NO;                    // output channels per workgroup
+  constexpr int NIN = PR * 34 * 4;               // 16-byte input pieces per chunk
+  constexpr int NW = 9 * CO * 4;                 // 16-byte weight pieces per chunk
+  constexpr int PIN = (NIN + 255) / 256;         // per thread
+  constexpr int PW = (NW + 255) / 256;
+  extern __shared__ __align__(16) bf16 lds_c[];
+  bf16* xin = lds_c;                             // [PR][34][kConvPad]
+  bf16* wts = lds_c + PR * 34 * kConvPad;        // [9][CO][kConvPad]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i = lane & 31, half = lane >> 5;
-  const int64_t p = p0 + i;
-  const int wc = (int)(p % a.w);
-  const int64_t r = p / a.w;
-  const int hr = (int)(r % a.h);
-  const int64_t img = r / a.h;
-  v16f C[NT];
-#pragma unroll
-  for (int n = 0; n < NT; ++n)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) C[n][v] = 0.f;
+  const int co0 = blockIdx.y * CO;
+  const int nch = a.k_in / 32;
+  const int t_begin = blockIdx.x * a.run;
+  const int t_end = min(a.n_tiles, t_begin + a.run);
+  const int n_items = (t_end - t_begin) * nch;
   const v8bf zero = {};
-  for (int t = 0; t < 9; ++t) {
-    int dh = t / 3 - 1, dw = t % 3 - 1;
-    if (a.flip) {
-      dh = -dh;
-      dw = -dw;
-    }
-    const int hh = hr + dh, ww = wc + dw;
-    const bool valid = hh >= 0 && hh < a.h && ww >= 0 && ww < a.w;
-    const bf16* xr = a.x + ((img * a.h + (valid ? hh : 0)) * a.w + (valid ? ww : 0)) * (int64_t)a.ldx + 8 * half;
-    const bf16* wr = a.wt + ((int64_t)(co0 + i) * 9 + t) * a.k_in + 8 * half;
-    const int64_t wstep = (int64_t)32 * 9 * a.k_in;   // next 32 output channels
-    // each input fragment feeds NT output tiles
-#pragma unroll 2
-    for (int k0 = 0; k0 < a.k_in; k0 += 16) {
-      const v8bf av = valid ? *reinterpret_cast<const v8bf*>(xr + k0) : zero;
+
+  v8bf pin[PIN], pw[PW];
+  // registers <- pieces of item `it` (tile t_begin + it / nch, chunk it % nch)
+  auto fetch = [&](int it, bool with_w) {
+    const int tile = t_begin + it / nch, k0 = 32 * (it % nch);
+    const int ct = tile % a.n_ct, rt = (tile / a.n_ct) % a.n_rt, img = tile / (a.n_ct * a.n_rt);
+    const int r0 = rt * 4 * RW, c0 = ct * 32;
 #pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const v8bf bv = *reinterpret_cast<const v8bf*>(wr + n * wstep + k0);
-        C[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, C[n], 0, 0, 0);
+    for (int j = 0; j < PIN; ++j) {
+      const int e = tid + 256 * j;
+      const int q = e & 3, pc = (e >> 2) % 34, pr = (e >> 2) / 34;
+      const int row = r0 - 1 + pr, col = c0 - 1 + pc;
+      pin[j] = zero;
+      if (e < NIN && row >= 0 && row < a.h && col >= 0 && col < a.w)
+        pin[j] = *reinterpret_cast<const v8bf*>(a.x + (((int64_t)img * a.h + row) * a.w + col) * (int64_t)a.ldx +
+                                                k0 + 8 * q);
+    }
+    if (with_w) {
+#pragma unroll
+      for (int j = 0; j < PW; ++j) {
+        const int e = tid + 256 * j;
+        const int q = e & 3, t = (e >> 2) % 9, o = (e >> 2) / 9;
+        if (e < NW) pw[j] = *reinterpret_cast<const v8bf*>(a.wt + ((int64_t)(co0 + o) * 9 + t) * a.k_in + k0 + 8 * q);
       }
     }
-  }
+  };
+  auto put = [&](bool with_w) {
 #pragma unroll
-  for (int n = 0; n < NT; ++n) {
-    const int co = co0 + 32 * n + i;
-    const float bb = (a.bias && !a.acc) ? a.bias[co] : 0.f;
+    for (int j = 0; j < PIN; ++j) {
+      const int e = tid + 256 * j;
+      const int q = e & 3, pc = (e >> 2) % 34, pr = (e >> 2) / 34;
+      if (e < NIN) *reinterpret_cast<v8bf*>(xin + (pr * 34 + pc) * kConvPad + 8 * q) = pin[j];
+    }
+    if (with_w) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = 8 * (v >> 2) + 4 * half + (v & 3);
-      bf16* dst = a.y + (p0 + row) * (int64_t)a.ldy + co;
-      float val = C[n][v] + bb;
-      if (a.acc) {
-        val += (float)*dst;
-      } else if (a.relu) {
-        val = fmaxf(val, 0.f);
+      for (int j = 0; j < PW; ++j) {
+        const int e = tid + 256 * j;
+        const int q = e & 3, t = (e >> 2) % 9, o = (e >> 2) / 9;
+        if (e < NW) *reinterpret_cast<v8bf*>(wts + (t * CO + o) * kConvPad + 8 * q) = pw[j];
       }
-      *dst = (bf16)val;
+    }
+  };
+
+  v16f C[RW][NO];
+  auto clear = [&]() {
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int n = 0; n < NO; ++n)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) C[r][n][v] = 0.f;
+  };
+  clear();
+  if (n_items > 0) fetch(0, true);
+  for (int it = 0; it < n_items; ++it) {
+    const bool w_now = nch > 1 || it == 0;       // weights of this item go to LDS
+    put(w_now);
+    __syncthreads();
+    if (it + 1 < n_items) fetch(it + 1, nch > 1);
+#pragma unroll 1
+    for (int t = 0; t < 9; ++t) {
+      int dh = t / 3 - 1, dw = t % 3 - 1;
+      if (a.flip) {
+        dh = -dh;
+        dw = -dw;
+      }
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        v8bf av[RW], bv[NO];
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+          av[r] = *reinterpret_cast<const v8bf*>(xin + ((RW * wv + r + 1 + dh) * 34 + i + 1 + dw) * kConvPad + 16 * ks +
+                                                 8 * half);
+#pragma unroll
+        for (int n = 0; n < NO; ++n)
+          bv[n] = *reinterpret_cast<const v8bf*>(wts + (t * CO + 32 * n + i) * kConvPad + 16 * ks + 8 * half);
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+          for (int n = 0; n < NO; ++n) C[r][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[r], bv[n], C[r][n], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (it % nch == nch - 1) {
+      // last chunk of the tile: bias / activation / accumulation and store
+      const int tile = t_begin + it / nch;
+      const int ct = tile % a.n_ct, rt = (tile / a.n_ct) % a.n_rt, img = tile / (a.n_ct * a.n_rt);
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int row = rt * 4 * RW + RW * wv + r;
+        if (row >= a.h) continue;
+        const int64_t p0 = ((int64_t)img * a.h + row) * a.w + ct * 32;
+#pragma unroll
+        for (int n = 0; n < NO; ++n) {
+          const int co = co0 + 32 * n + i;
+          const float bb = (a.bias && !a.acc) ? a.bias[co] : 0.f;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int px = 8 * (v >> 2) + 4 * half + (v & 3);
+            bf16* dst = a.y + (p0 + px) * (int64_t)a.ldy + co;
+            float val = C[r][n][v] + bb;
+            if (a.acc) {
+              val += (float)*dst;
+            } else if (a.relu) {
+              val = fmaxf(val, 0.f);
+            }
+            *dst = (bf16)val;
+          }
+        }
+      }
+      clear();
     }
   }
 }
@@ -253,6 +348,105 @@ __global__ void upsample_bwd_kernel(const bf16* dy, int32_t lddy, int64_t n, int
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + expf(-z)); }
 __device__ __forceinline__ float softplusf_(float x) { return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x))); }
 
+// The same four operations on 8 channels (16 bytes) per thread, for channel counts and
+// strides that are multiples of 8 on 16-byte aligned tensors (every tensor of the network).
+__global__ void maxpool8_kernel(const bf16* x, int32_t ldx, int64_t n8, int32_t h, int32_t w, int32_t c8, bf16* y,
+                                int32_t ldy, uint8_t* arg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n8) return;  // n8 = batch * (h/2) * (w/2) * c/8
+  const int k = (int)(e % c8) * 8;
+  const int64_t q = e / c8;
+  const int wo = (int)(q % (w / 2));
+  const int64_t r = q / (w / 2);
+  const int ho = (int)(r % (h / 2));
+  const int64_t img = r / (h / 2);
+  const int64_t base = (img * h + 2 * ho) * (int64_t)w + 2 * wo;
+  const v8bf v[4] = {*reinterpret_cast<const v8bf*>(x + base * ldx + k),
+                     *reinterpret_cast<const v8bf*>(x + (base + 1) * ldx + k),
+                     *reinterpret_cast<const v8bf*>(x + (base + w) * ldx + k),
+                     *reinterpret_cast<const v8bf*>(x + (base + w + 1) * ldx + k)};
+  v8bf out;
+  uint64_t bests = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    int best = 0;
+    float bv = (float)v[0][j];
+#pragma unroll
+    for (int m = 1; m < 4; ++m)
+      if ((float)v[m][j] > bv) {
+        bv = (float)v[m][j];
+        best = m;
+      }
+    out[j] = v[best][j];
+    bests |= (uint64_t)best << (8 * j);
+  }
+  *reinterpret_cast<v8bf*>(y + q * ldy + k) = out;
+  *reinterpret_cast<uint64_t*>(arg + e * 8) = bests;
+}
+
+__global__ void maxpool8_bwd_kernel(const bf16* dy, int32_t lddy, const uint8_t* arg, int64_t n8, int32_t h,
+                                    int32_t w, int32_t c8, bf16* dx, int32_t lddx, int32_t accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n8) return;
+  const int k = (int)(e % c8) * 8;
+  const int64_t q = e / c8;
+  const int wo = (int)(q % (w / 2));
+  const int64_t r = q / (w / 2);
+  const int ho = (int)(r % (h / 2));
+  const int64_t img = r / (h / 2);
+  const int64_t base = (img * h + 2 * ho) * (int64_t)w + 2 * wo;
+  const int64_t pos[4] = {base, base + 1, base + w, base + w + 1};
+  const v8bf g = *reinterpret_cast<const v8bf*>(dy + q * lddy + k);
+  const uint64_t bests = *reinterpret_cast<const uint64_t*>(arg + e * 8);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    v8bf* d = reinterpret_cast<v8bf*>(dx + pos[m] * lddx + k);
+    const v8bf old = accumulate ? *d : v8bf{};
+    v8bf o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float add = (int)((bests >> (8 * j)) & 0xff) == m ? (float)g[j] : 0.f;
+      o[j] = (bf16)(accumulate ? (float)old[j] + add : add);
+    }
+    *d = o;
+  }
+}
+
+__global__ void upsample8_kernel(const bf16* x, int32_t ldx, int64_t n8, int32_t h, int32_t w, int32_t c8, bf16* y,
+                                 int32_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n8) return;  // n8 = batch * (2h) * (2w) * c/8
+  const int k = (int)(e % c8) * 8;
+  const int64_t q = e / c8;
+  const int wo = (int)(q % (2 * w));
+  const int64_t r = q / (2 * w);
+  const int ho = (int)(r % (2 * h));
+  const int64_t img = r / (2 * h);
+  *reinterpret_cast<v8bf*>(y + q * ldy + k) =
+      *reinterpret_cast<const v8bf*>(x + ((img * h + ho / 2) * w + wo / 2) * (int64_t)ldx + k);
+}
+
+__global__ void upsample8_bwd_kernel(const bf16* dy, int32_t lddy, int64_t n8, int32_t h, int32_t w, int32_t c8,
+                                     bf16* dx, int32_t lddx) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n8) return;  // n8 = batch * h * w * c/8 (sizes of dx)
+  const int k = (int)(e % c8) * 8;
+  const int64_t q = e / c8;
+  const int wc = (int)(q % w);
+  const int64_t r = q / w;
+  const int hr = (int)(r % h);
+  const int64_t img = r / h;
+  const int64_t base = (img * 2 * h + 2 * hr) * (int64_t)(2 * w) + 2 * wc;
+  const v8bf a = *reinterpret_cast<const v8bf*>(dy + base * lddy + k);
+  const v8bf b = *reinterpret_cast<const v8bf*>(dy + (base + 1) * lddy + k);
+  const v8bf c = *reinterpret_cast<const v8bf*>(dy + (base + 2 * w) * lddy + k);
+  const v8bf d = *reinterpret_cast<const v8bf*>(dy + (base + 2 * w + 1) * lddy + k);
+  v8bf o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = (bf16)((float)a[j] + (float)b[j] + (float)c[j] + (float)d[j]);
+  *reinterpret_cast<v8bf*>(dx + q * lddx + k) = o;
+}
+
 __global__ __launch_bounds__(256) void head_kernel(const bf16* feat, int32_t c, int64_t P, const float* w,
                                                    const float* b, const float* target, const float* weight,
                                                    float* mask, float* err, float* dz, float* loss,
@@ -262,10 +456,22 @@ __global__ __launch_bounds__(256) void head_kernel(const bf16* feat, int32_t c, 
   float l0 = 0.f, l1 = 0.f, l2 = 0.f;
   if (p < P) {
     float z0 = b[0], z1 = b[1];
-    for (int k = 0; k < c; ++k) {
-      const float f = (float)feat[p * c + k];
-      z0 = fmaf(f, w[2 * k], z0);
-      z1 = fmaf(f, w[2 * k + 1], z1);
+    if ((c & 7) == 0) {
+      for (int k = 0; k < c; k += 8) {
+        const v8bf f8 = *reinterpret_cast<const v8bf*>(feat + p * c + k);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float f = (float)f8[j];
+          z0 = fmaf(f, w[2 * (k + j)], z0);
+          z1 = fmaf(f, w[2 * (k + j) + 1], z1);
+        }
+      }
+    } else {
+      for (int k = 0; k < c; ++k) {
+        const float f = (float)feat[p * c + k];
+        z0 = fmaf(f, w[2 * k], z0);
+        z1 = fmaf(f, w[2 * k + 1], z1);
+      }
     }
     const float m = sigmoidf_(z0), e = sigmoidf_(z1);
     mask[p] = m;
@@ -401,36 +607,54 @@ __global__ __launch_bounds__(1024) void features_kernel(const float* E, int64_t 
   }
 }
 
-// Input features from the adjacent-pixel cross-spectra of a full-aperture field: one
-// workgroup per frame.  Pass 1 sums the channels over the bin splits into the energy
-// (S) and finds its maximum; pass 2 writes the eight feature channels of every pixel.
-// A pair's normalised cross-spectrum is taken at its even member (left column, upper
-// depth), so both pixels of a pair see the same oriented value.
-__global__ __launch_bounds__(1024) void coherence_features_kernel(const float* acc, int32_t n_split, int64_t sstride,
-                                                                  int32_t n_z, int32_t n_x, bf16* out, float* energy) {
-  __shared__ float red[1024];
-  const int64_t f = blockIdx.x;
-  const int64_t P = (int64_t)n_z * n_x;
-  const float* a0 = acc + f * 5 * P;
-  float* e = energy + f * P;
-  auto chan = [&](int c, int64_t p) {
-    float v = 0.f;
-    for (int s = 0; s < n_split; ++s) v += a0[s * sstride + c * P + p];
-    return v;
-  };
-  float m = 0.f;
-  for (int64_t p = threadIdx.x; p < P; p += 1024) {
-    const float v = chan(0, p);
-    e[p] = v;
-    m = fmaxf(m, v);
+// Input features from the adjacent-pixel cross-spectra of a full-aperture field, in
+// three launches over (pixel block, frame): clear the per-frame maxima; sum the channels
+// over the bin splits into the energy (S) and raise the frame's maximum (S >= 0, so its
+// bit pattern orders like the value: an integer atomic max); write the eight feature
+// channels of every pixel.  A pair's normalised cross-spectrum is taken at its even
+// member (left column, upper depth), so both pixels of a pair see the same oriented value.
+__global__ void clear_max_kernel(unsigned* fmax, int32_t n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) fmax[k] = 0u;
+}
+
+__global__ __launch_bounds__(256) void energy_max_kernel(const float* acc, int32_t n_split, int64_t sstride,
+                                                         int64_t P, float* energy, unsigned* fmax) {
+  __shared__ float red[256];
+  const int64_t f = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float v = 0.f;
+  if (p < P) {
+    const float* a0 = acc + f * 5 * P + p;
+    for (int s = 0; s < n_split; ++s) v += a0[s * sstride];
+    v = fmaxf(v, 0.f);
+    energy[f * P + p] = v;
   }
-  red[threadIdx.x] = m;
+  red[threadIdx.x] = v;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  const float inv = red[0] > 0.f ? 1.f / red[0] : 1.f;
+  if (threadIdx.x == 0) atomicMax(fmax + f, __float_as_uint(red[0]));
+}
+
+__global__ __launch_bounds__(256) void coherence_features_kernel(const float* acc, int32_t n_split, int64_t sstride,
+                                                                 int32_t n_z, int32_t n_x, const float* energy,
+                                                                 const unsigned* fmax, bf16* out) {
+  const int64_t f = blockIdx.y;
+  const int64_t P = (int64_t)n_z * n_x;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  const float* a0 = acc + f * 5 * P;
+  const float* e = energy + f * P;
+  auto chan = [&](int c, int64_t q) {
+    float v = 0.f;
+    for (int s = 0; s < n_split; ++s) v += a0[s * sstride + c * P + q];
+    return v;
+  };
+  const float mx = __uint_as_float(fmax[f]);
+  const float inv = mx > 0.f ? 1.f / mx : 1.f;
   auto coh = [&](int64_t q0, int64_t q1, int c, float* o) {   // |c|, Re c, Im c of the pair (q0, q1)
     const float d = e[q0] * e[q1];
     if (!(d > 0.f)) {
@@ -443,27 +667,25 @@ __global__ __launch_bounds__(1024) void coherence_features_kernel(const float* a
     o[1] = re;
     o[2] = im;
   };
-  for (int64_t p = threadIdx.x; p < P; p += 1024) {
-    const int x = (int)(p % n_x), z = (int)(p / n_x);
-    const float r = e[p] * inv;
-    float cx[3], cz[3];
-    coh((int64_t)z * n_x + (x & ~1), (int64_t)z * n_x + (x | 1), 1, cx);
-    coh((int64_t)(z & ~1) * n_x + x, (int64_t)(z | 1) * n_x + x, 3, cz);
-    v8bf lo, z8 = {};
-    lo[0] = (bf16)fminf(fmaxf(log10f(fmaxf(r, 1e-30f)) / 6.f + 1.f, 0.f), 1.f);
-    lo[1] = (bf16)r;
-    lo[2] = (bf16)cx[0];
-    lo[3] = (bf16)cx[1];
-    lo[4] = (bf16)cx[2];
-    lo[5] = (bf16)cz[0];
-    lo[6] = (bf16)cz[1];
-    lo[7] = (bf16)cz[2];
-    v8bf* dst = reinterpret_cast<v8bf*>(out + (f * P + p) * 32);
-    dst[0] = lo;
-    dst[1] = z8;
-    dst[2] = z8;
-    dst[3] = z8;
-  }
+  const int x = (int)(p % n_x), z = (int)(p / n_x);
+  const float r = e[p] * inv;
+  float cx[3], cz[3];
+  coh((int64_t)z * n_x + (x & ~1), (int64_t)z * n_x + (x | 1), 1, cx);
+  coh((int64_t)(z & ~1) * n_x + x, (int64_t)(z | 1) * n_x + x, 3, cz);
+  v8bf lo, z8 = {};
+  lo[0] = (bf16)fminf(fmaxf(log10f(fmaxf(r, 1e-30f)) / 6.f + 1.f, 0.f), 1.f);
+  lo[1] = (bf16)r;
+  lo[2] = (bf16)cx[0];
+  lo[3] = (bf16)cx[1];
+  lo[4] = (bf16)cx[2];
+  lo[5] = (bf16)cz[0];
+  lo[6] = (bf16)cz[1];
+  lo[7] = (bf16)cz[2];
+  v8bf* dst = reinterpret_cast<v8bf*>(out + (f * P + p) * 32);
+  dst[0] = lo;
+  dst[1] = z8;
+  dst[2] = z8;
+  dst[3] = z8;
 }
 
 // Predicted relative L2 error of a frame's image: with the image mask^2 E and a mask
@@ -524,6 +746,10 @@ __global__ void apply_mask_kernel(const float* mask, const float* E, float* imag
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+// 8-channel vector form applies: channel count and strides multiples of 8, 16-byte aligned bases
+inline bool vec8(int c, int ld_a, int ld_b, const void* a, const void* b) {
+  return c % 8 == 0 && ld_a % 8 == 0 && ld_b % 8 == 0 && aligned16(a) && aligned16(b);
+}
 
 }  // namespace
 
@@ -532,20 +758,35 @@ extern "C" {
 pam_status_t pam_nn_conv3x3(const void* x, int32_t ldx, int32_t batch, int32_t h, int32_t w, int32_t k_in,
                             const void* wt, const float* bias, void* y, int32_t ldy, int32_t n_out, int32_t relu,
                             int32_t flip, int32_t accumulate, void* hip_stream) {
-  if (!x || !wt || !y || batch < 1 || h < 1 || w < 32 || w % 32 || k_in < 16 || k_in % 16 || n_out < 32 ||
+  if (!x || !wt || !y || batch < 1 || h < 1 || w < 32 || w % 32 || k_in < 32 || k_in % 32 || n_out < 32 ||
       n_out % 32 || ldx < k_in || ldx % 8 || ldy < n_out || !aligned16(x) || !aligned16(wt))
     return PAM_ERR_INVALID_ARG;
-  ConvArgs a{static_cast<const bf16*>(x), static_cast<const bf16*>(wt), bias, static_cast<bf16*>(y),
-             (int64_t)batch * h * w, ldx, h, w, k_in, ldy, n_out, relu, flip, accumulate};
-  const int64_t tiles = a.P / 32;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // 32 pixels x 32 NT output channels per wave
-  if (n_out % 128 == 0)
-    hipLaunchKernelGGL(conv3x3_kernel<4>, dim3(blocks_for(tiles, 4), n_out / 128), dim3(256), 0, st, a);
-  else if (n_out % 64 == 0)
-    hipLaunchKernelGGL(conv3x3_kernel<2>, dim3(blocks_for(tiles, 4), n_out / 64), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(conv3x3_kernel<1>, dim3(blocks_for(tiles, 4), n_out / 32), dim3(256), 0, st, a);
+  ConvArgs a{static_cast<const bf16*>(x), static_cast<const bf16*>(wt), bias, static_cast<bf16*>(y), ldx, batch, h,
+             w, k_in, ldy, n_out, relu, flip, accumulate, 0, w / 32, 0, 1};
+  // 64 output channels x 8 rows per tile where the channels allow, else 32 x 16; runs of
+  // up to 8 tiles per workgroup, as long as about 512 workgroups (two per CU, the LDS
+  // limit) remain
+  const bool wide = n_out % 64 == 0;
+  const int rows = wide ? 8 : 16, groups = n_out / (wide ? 64 : 32);
+  a.n_rt = (h + rows - 1) / rows;
+  const int64_t tiles = (int64_t)batch * a.n_rt * a.n_ct;
+  if (tiles > 0x7fffffffLL) return PAM_ERR_INVALID_ARG;
+  a.n_tiles = (int)tiles;
+  a.run = (int)std::max<int64_t>(1, std::min<int64_t>(8, tiles * groups / 512));
+  const dim3 grid((unsigned)((tiles + a.run - 1) / a.run), groups);
+  // (more than 64 KB of LDS: the kernel attribute is set before each launch)
+  if (wide) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(conv3x3_kernel<2, 2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, conv_lds_bytes<2, 2>()) != hipSuccess)
+      return PAM_ERR_DEVICE;
+    hipLaunchKernelGGL((conv3x3_kernel<2, 2>), grid, dim3(256), (conv_lds_bytes<2, 2>()), st, a);
+  } else {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(conv3x3_kernel<4, 1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, conv_lds_bytes<4, 1>()) != hipSuccess)
+      return PAM_ERR_DEVICE;
+    hipLaunchKernelGGL((conv3x3_kernel<4, 1>), grid, dim3(256), (conv_lds_bytes<4, 1>()), st, a);
+  }
   return launched();
 }
 
@@ -583,8 +824,13 @@ pam_status_t pam_nn_maxpool(const void* x, int32_t ldx, int32_t batch, int32_t h
   if (!x || !y || !arg || batch < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 1 || ldx < c || ldy < c)
     return PAM_ERR_INVALID_ARG;
   const int64_t n = (int64_t)batch * (h / 2) * (w / 2) * c;
-  hipLaunchKernelGGL(maxpool_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
-                     static_cast<const bf16*>(x), ldx, n, h, w, c, static_cast<bf16*>(y), ldy, arg);
+  if (vec8(c, ldx, ldy, x, y) && (reinterpret_cast<uintptr_t>(arg) & 7u) == 0)
+    hipLaunchKernelGGL(maxpool8_kernel, dim3(blocks_for(n / 8, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<const bf16*>(x), ldx, n / 8, h, w, c / 8,
+                       static_cast<bf16*>(y), ldy, arg);
+  else
+    hipLaunchKernelGGL(maxpool_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                       static_cast<const bf16*>(x), ldx, n, h, w, c, static_cast<bf16*>(y), ldy, arg);
   return launched();
 }
 
@@ -594,9 +840,14 @@ pam_status_t pam_nn_maxpool_backward(const void* dy, int32_t lddy, const uint8_t
   if (!dy || !arg || !dx || batch < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 1 || lddy < c || lddx < c)
     return PAM_ERR_INVALID_ARG;
   const int64_t n = (int64_t)batch * (h / 2) * (w / 2) * c;
-  hipLaunchKernelGGL(maxpool_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
-                     static_cast<hipStream_t>(hip_stream), static_cast<const bf16*>(dy), lddy, arg, n, h, w, c,
-                     static_cast<bf16*>(dx), lddx, accumulate);
+  if (vec8(c, lddy, lddx, dy, dx) && (reinterpret_cast<uintptr_t>(arg) & 7u) == 0)
+    hipLaunchKernelGGL(maxpool8_bwd_kernel, dim3(blocks_for(n / 8, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<const bf16*>(dy), lddy, arg, n / 8, h, w,
+                       c / 8, static_cast<bf16*>(dx), lddx, accumulate);
+  else
+    hipLaunchKernelGGL(maxpool_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<const bf16*>(dy), lddy, arg, n, h, w, c,
+                       static_cast<bf16*>(dx), lddx, accumulate);
   return launched();
 }
 
@@ -604,8 +855,13 @@ pam_status_t pam_nn_upsample(const void* x, int32_t ldx, int32_t batch, int32_t 
                              int32_t ldy, void* hip_stream) {
   if (!x || !y || batch < 1 || h < 1 || w < 1 || c < 1 || ldx < c || ldy < c) return PAM_ERR_INVALID_ARG;
   const int64_t n = (int64_t)batch * 4 * h * w * c;
-  hipLaunchKernelGGL(upsample_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
-                     static_cast<const bf16*>(x), ldx, n, h, w, c, static_cast<bf16*>(y), ldy);
+  if (vec8(c, ldx, ldy, x, y))
+    hipLaunchKernelGGL(upsample8_kernel, dim3(blocks_for(n / 8, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<const bf16*>(x), ldx, n / 8, h, w, c / 8,
+                       static_cast<bf16*>(y), ldy);
+  else
+    hipLaunchKernelGGL(upsample_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                       static_cast<const bf16*>(x), ldx, n, h, w, c, static_cast<bf16*>(y), ldy);
   return launched();
 }
 
@@ -613,9 +869,14 @@ pam_status_t pam_nn_upsample_backward(const void* dy, int32_t lddy, int32_t batc
                                       void* dx, int32_t lddx, void* hip_stream) {
   if (!dy || !dx || batch < 1 || h < 1 || w < 1 || c < 1 || lddy < c || lddx < c) return PAM_ERR_INVALID_ARG;
   const int64_t n = (int64_t)batch * h * w * c;
-  hipLaunchKernelGGL(upsample_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
-                     static_cast<hipStream_t>(hip_stream), static_cast<const bf16*>(dy), lddy, n, h, w, c,
-                     static_cast<bf16*>(dx), lddx);
+  if (vec8(c, lddy, lddx, dy, dx))
+    hipLaunchKernelGGL(upsample8_bwd_kernel, dim3(blocks_for(n / 8, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<const bf16*>(dy), lddy, n / 8, h, w, c / 8,
+                       static_cast<bf16*>(dx), lddx);
+  else
+    hipLaunchKernelGGL(upsample_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<const bf16*>(dy), lddy, n, h, w, c,
+                       static_cast<bf16*>(dx), lddx);
   return launched();
 }
 
@@ -678,12 +939,19 @@ pam_status_t pam_nn_features(const float* energy, int32_t batch, int64_t pixels,
 }
 
 pam_status_t pam_nn_coherence_features(const float* accum, int32_t n_split, int64_t split_stride, int32_t batch,
-                                       int32_t n_z, int32_t n_x, void* out, float* energy, void* hip_stream) {
-  if (!accum || !out || !energy || n_split < 1 || batch < 1 || n_z < 2 || n_x < 2 || (n_z & 1) || (n_x & 1) ||
-      (n_split > 1 && split_stride < (int64_t)batch * 5 * n_z * n_x) || !aligned16(out))
+                                       int32_t n_z, int32_t n_x, void* out, float* energy, float* frame_max,
+                                       void* hip_stream) {
+  if (!accum || !out || !energy || !frame_max || n_split < 1 || batch < 1 || batch > 65535 || n_z < 2 || n_x < 2 ||
+      (n_z & 1) || (n_x & 1) || (n_split > 1 && split_stride < (int64_t)batch * 5 * n_z * n_x) || !aligned16(out))
     return PAM_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(coherence_features_kernel, dim3(batch), dim3(1024), 0, static_cast<hipStream_t>(hip_stream), accum,
-                     n_split, split_stride, n_z, n_x, static_cast<bf16*>(out), energy);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t P = (int64_t)n_z * n_x;
+  unsigned* fm = reinterpret_cast<unsigned*>(frame_max);
+  const dim3 grid(blocks_for(P, 256), batch);
+  hipLaunchKernelGGL(clear_max_kernel, dim3(blocks_for(batch, 256)), dim3(256), 0, st, fm, batch);
+  hipLaunchKernelGGL(energy_max_kernel, grid, dim3(256), 0, st, accum, n_split, split_stride, P, energy, fm);
+  hipLaunchKernelGGL(coherence_features_kernel, grid, dim3(256), 0, st, accum, n_split, split_stride, n_z, n_x,
+                     energy, fm, static_cast<bf16*>(out));
   return launched();
 }
 

@@ -33,7 +33,7 @@ def lib():
             "pam_nn_features": [vp, i32, i64, vp, vp],
             "pam_nn_confidence": [vp, vp, i32, i64, vp, vp],
             "pam_nn_apply_mask": [vp, vp, vp, i64, vp],
-            "pam_nn_coherence_features": [vp, i32, i64, i32, i32, i32, vp, vp, vp],
+            "pam_nn_coherence_features": [vp, i32, i64, i32, i32, i32, vp, vp, vp, vp],
             "pam_nn_error_estimate": [vp, vp, vp, i32, i64, vp, vp],
         }
         for name, args in sig.items():
@@ -121,9 +121,9 @@ def apply_mask(mask, energy, image, stream=None):
     _call("pam_nn_apply_mask", _p(mask), _p(energy), _p(image), mask.numel(), _s(stream))
 
 
-def coherence_features(accum, n_split, split_stride, batch, n_z, n_x, out, energy, stream=None):
+def coherence_features(accum, n_split, split_stride, batch, n_z, n_x, out, energy, frame_max, stream=None):
     _call("pam_nn_coherence_features", _p(accum), n_split, split_stride, batch, n_z, n_x, _p(out), _p(energy),
-          _s(stream))
+          _p(frame_max), _s(stream))
 
 
 def error_estimate(mask, err, energy, batch, pixels, est, stream=None):

@@ -384,10 +384,11 @@ def build_dataset(seeds, geom, chunk: int = 64, workers: int = 16, log=None, kin
     return torch.cat(A), torch.cat(R)
 
 
-def features(A, feats, energy):
-    """Network input and energy of frames A (FP32 [b][5][n_z][n_x], one split)."""
+def features(A, feats, energy, fmax):
+    """Network input, energy and per-frame maximum energy of frames A (FP32 [b][5][n_z][n_x],
+    one split)."""
     b, _, H, W = A.shape
-    nn.coherence_features(A, 1, 0, b, H, W, feats, energy)
+    nn.coherence_features(A, 1, 0, b, H, W, feats, energy, fmax)
 
 
 # ----------------------------------------------------------------------------
@@ -403,6 +404,7 @@ def train(net: UNet, A, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: i
     feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
     e = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
     wts = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
+    fmax = torch.empty(batch, dtype=torch.float32, device=net.device)
     rng = np.random.default_rng(seed)
     hist = []
     t0 = time.perf_counter()
@@ -410,7 +412,7 @@ def train(net: UNet, A, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: i
         idx = torch.as_tensor(rng.choice(n, size=batch, replace=False), device=net.device)
         a = A.index_select(0, idx).contiguous()
         r = R.index_select(0, idx).contiguous()
-        features(a, feats, e)
+        features(a, feats, e, fmax)
         nn.loss_weights(e, batch, H * W, mix, wts)
         net.forward(feats, batch, H, W)
         loss = net.loss_backward(r, wts)
@@ -438,10 +440,11 @@ def predict(net: UNet, A, batch: int = 8):
     n, _, H, W = A.shape
     feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
     e = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
+    fmax = torch.empty(batch, dtype=torch.float32, device=net.device)
     masks, errs, ests = [], [], []
     for i in range(0, n, batch):
         b = min(batch, n - i)
-        features(A[i:i + b].contiguous(), feats, e)
+        features(A[i:i + b].contiguous(), feats, e, fmax)
         m, er, est = _infer(net, feats, e, b, H, W)
         masks.append(m.clone())
         errs.append(er.clone())
@@ -477,7 +480,7 @@ class SurrogatePipeline:
     (tau < 0: every frame; tau = inf: none)."""
 
     def __init__(self, geom, net: UNet, tau: float, precision: str = "fp32", max_frames: int = 64,
-                 batch: int = 8):
+                 batch: int = 16):
         import torch
         self.torch = torch
         self.geom, self.net, self.tau = geom, net, tau
@@ -487,6 +490,7 @@ class SurrogatePipeline:
         H, W = self.fa.plan.n_z, self.fa.plan.n_x
         self.feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
         self.e = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
+        self.fmax = torch.empty(batch, dtype=torch.float32, device=net.device)
 
     def __call__(self, rf):
         torch = self.torch
@@ -498,7 +502,7 @@ class SurrogatePipeline:
         est = torch.empty(F, dtype=torch.float32, device=rf.device)
         for i in range(0, F, self.batch):
             b = min(self.batch, F - i)
-            nn.coherence_features(acc[i * 5 * P:], n_split, F * 5 * P, b, H, W, self.feats, self.e)
+            nn.coherence_features(acc[i * 5 * P:], n_split, F * 5 * P, b, H, W, self.feats, self.e, self.fmax)
             m, _, es = _infer(self.net, self.feats, self.e, b, H, W)
             mask[i:i + b].copy_(m)
             est[i:i + b].copy_(es)

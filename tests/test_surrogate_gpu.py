@@ -196,12 +196,14 @@ def test_coherence_features_definition(env):
     dev = torch.from_numpy(acc.astype(np.float32)).cuda()
     out = torch.zeros((F, H, W, S.C_FEAT), dtype=torch.bfloat16, device="cuda")
     e = torch.empty((F, H, W), device="cuda")
-    nn.coherence_features(dev.view(-1), n_split, F * 5 * P, F, H, W, out, e)
+    fmax = torch.full((F,), -1.0, device="cuda")
+    nn.coherence_features(dev.view(-1), n_split, F * 5 * P, F, H, W, out, e, fmax)
     got = out.float().cpu().numpy()
     a = acc.astype(np.float32).astype(np.float64).sum(0)     # [F][5][H][W]
     S_ = a[:, 0]
     np.testing.assert_allclose(e.cpu().numpy(), S_, rtol=1e-6)
     mx = S_.reshape(F, -1).max(1)[:, None, None]
+    np.testing.assert_allclose(fmax.cpu().numpy(), mx.ravel(), rtol=1e-6)
     r = S_ / mx
     want = np.zeros((F, H, W, 8))
     want[..., 0] = np.clip(np.log10(np.maximum(r, 1e-30)) / 6 + 1, 0, 1)
@@ -229,3 +231,53 @@ def test_error_estimate_definition(env):
     mf, ef, Ef = (v.cpu().numpy().astype(np.float64) for v in t)
     want = np.linalg.norm(2 * mf * ef * Ef, axis=1) / np.linalg.norm(mf * mf * Ef, axis=1)
     np.testing.assert_allclose(est.cpu().numpy(), want, rtol=1e-5)
+
+
+@pytest.mark.parametrize("h,w,k_in,n_out,ldx_pad,mode", [
+    (13, 64, 64, 32, 0, "relu"),        # 16-row tiling, ragged rows
+    (8, 32, 96, 64, 32, "relu"),        # 8-row tiling, channel stride > k_in
+    (21, 96, 32, 96, 0, "flip"),        # 96 outputs (three 32-channel groups), input-gradient taps
+    (10, 64, 128, 128, 0, "accumulate"),
+])
+def test_conv3x3_against_reference(env, h, w, k_in, n_out, ldx_pad, mode):
+    """One convolution on BF16 operands against the FP64 reference of the same BF16 values:
+    the only differences are the FP32 accumulation order and the BF16 rounding of the output."""
+    torch, nn, S = env
+    rng = np.random.default_rng(h * w + k_in)
+    B = 2
+    x = bf16_round(rng.standard_normal((B, h, w, k_in)))
+    W = bf16_round(rng.standard_normal((9, k_in, n_out)) / np.sqrt(9 * k_in))
+    b = rng.standard_normal(n_out) * 0.1
+    ldx = k_in + ldx_pad
+    xd = torch.zeros((B, h, w, ldx), dtype=torch.bfloat16, device="cuda")
+    xd[..., :k_in] = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16)
+    Wd = torch.tensor(W, dtype=torch.float32, device="cuda")
+    wt = torch.empty((n_out, 9, k_in), dtype=torch.bfloat16, device="cuda")
+    wd = torch.empty((k_in, 9, n_out), dtype=torch.bfloat16, device="cuda")
+    nn.pack_weights(Wd, k_in, n_out, wt, wd)
+    bias = torch.tensor(b, dtype=torch.float32, device="cuda")
+    if mode == "flip":
+        # gradient with respect to the input of a conv with n_out inputs and k_in outputs:
+        # dx = sum_t shift_{-t}(dy) W[t]^T, with dy the x above and W's transpose as weights
+        Wt = bf16_round(rng.standard_normal((9, n_out, k_in)) / np.sqrt(9 * k_in))
+        Wtd = torch.tensor(Wt, dtype=torch.float32, device="cuda")
+        wt2 = torch.empty((k_in, 9, n_out), dtype=torch.bfloat16, device="cuda")
+        wd2 = torch.empty((n_out, 9, k_in), dtype=torch.bfloat16, device="cuda")
+        nn.pack_weights(Wtd, n_out, k_in, wt2, wd2)
+        y = torch.empty((B, h, w, n_out), dtype=torch.bfloat16, device="cuda")
+        nn.conv3x3(xd, ldx, B, h, w, k_in, wd2, None, y, n_out, n_out, relu=False, flip=True)
+        want = np.stack([U.conv3x3_backward(np.zeros((h, w, n_out)), Wt, x[i])[0] for i in range(B)])
+    else:
+        prev = bf16_round(rng.standard_normal((B, h, w, n_out)))
+        y = torch.tensor(prev, dtype=torch.float32).to(torch.bfloat16).cuda()
+        acc = mode == "accumulate"
+        nn.conv3x3(xd, ldx, B, h, w, k_in, wt, None if acc else bias, y, n_out, n_out, relu=not acc,
+                   accumulate=acc)
+        want = np.stack([U.conv3x3(x[i], W, np.zeros(n_out) if acc else b) for i in range(B)])
+        want = want + prev if acc else np.maximum(want, 0.0)
+    got = y.float().cpu().numpy()
+    scale = np.abs(want).max()
+    err = np.abs(got - want).max() / scale
+    print(f"max err / max |y| = {err:.2e}", flush=True)
+    assert err < 2 ** -7
+    assert rel(got, want) < 2 ** -8
