@@ -281,3 +281,38 @@ def test_conv3x3_against_reference(env, h, w, k_in, n_out, ldx_pad, mode):
     print(f"max err / max |y| = {err:.2e}", flush=True)
     assert err < 2 ** -7
     assert rel(got, want) < 2 ** -8
+
+
+def test_shipped_calibration_on_benchmark_frames(env):
+    """The shipped weights on fresh benchmark-geometry frames (seeds outside every training,
+    calibration and evaluation set): fallback frames are plain AS-TAX exactly, and frames
+    accepted with an image error above the calibrated bound stay within the calibration's
+    level alpha (the split-conformal guarantee bounds their expected rate by alpha; a
+    margin covers the sampling spread of 32 frames)."""
+    import math
+    import os
+    torch, nn, S = env
+    from paper_2412_02413_amd import synth
+    path = os.path.join(os.path.dirname(S.__file__), "weights", "surrogate_l4_b32_coh.safetensors")
+    net, calibration = S.UNet.from_weights(path)
+    g = synth.cfg2_geometry()
+    cal = calibration[S.geometry_key(g)]
+    assert 0 < cal["tau"] < math.inf and cal["bound"] > 0 and 0 < cal["alpha"] < 1
+    rf = torch.from_numpy(S.generate_rf(list(range(6_000_000, 6_000_032)), 0, "headline")).cuda()
+    pipe = S.SurrogatePipeline(g, net, tau=cal["tau"], max_frames=32)
+    teacher = S.Teacher(g, max_frames=32)
+    try:
+        image, mask, est, fb = pipe(rf)
+        _, plain = teacher(rf)
+        torch.cuda.synchronize()
+    finally:
+        pipe.close()
+        teacher.close()
+    fb_t = torch.as_tensor(fb, device="cuda")
+    assert torch.equal(image[fb_t], plain[fb_t])
+    err = ((image - plain).flatten(1).norm(dim=1) / plain.flatten(1).norm(dim=1)).cpu().numpy()
+    over = (~fb) & (err > cal["bound"])
+    print(f"fallback {fb.mean():.3f}, accepted over the bound {over.mean():.3f}, accepted error "
+          f"max {err[~fb].max() if (~fb).any() else 0:.3f}", flush=True)
+    assert np.all((est.cpu().numpy() > cal["tau"]) == fb)
+    assert over.mean() <= cal["alpha"] + 0.1
