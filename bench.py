@@ -8,11 +8,13 @@ paper's recordings are not available).
 
 Prints ONE JSON line on stdout:
   * throughput (frames/s) and single-frame latency p50/p99 of the main form;
-  * the dominant kernel (fields: propagator + two-stage DFT-GEMM + cross-spectra)
-    against its roofline, timed live with HIP events on the library's stream:
-    `frac` counts the method's own algorithmic flops (lateral inverse FFTs,
-    propagator products, cross-spectra sums), `mfma_util` the matrix-core flops
-    the kernel executes;
+  * the dominant kernel (fields: propagator + two-stage inverse lateral transform +
+    cross-spectra) against its roofline, timed live with HIP events on the library's
+    stream: `frac` counts the method's own algorithmic flops (lateral inverse FFTs,
+    propagator products, cross-spectra sums).  In FP32 the transform is a 16 x 16 FFT
+    on the vector ALUs (bound "alu", FP32 vector peak); the 16-bit forms run it as
+    DFT-GEMMs on the matrix cores (bound "mfma", with `mfma_util` the matrix-core
+    flops they execute);
   * the other operand forms of the DFT-GEMM on the same frames;
   * the error of every form against the FP64 oracle (max and mean over 16 frames
     of this workload and 64 frames of the 64-element workload), computed by oracle
@@ -47,6 +49,8 @@ if ROOT not in sys.path:
 METRIC = "AS-TAX frames/s and p99 ms/frame (128ch, 256×512); surrogate/split vs plain"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0, "bf16": 2500.0, "fp16": 2500.0}
+VALU_FP32_PEAK_TFLOPS = 157.3          # 256 CUs x 2.4 GHz x 256 FP32 flops per clock (packed FMA)
+VALU_FP32_UNPACKED_TFLOPS = 78.6       # the same without packed FP32 instructions (not used in this build)
 MFMA_PASSES = {"fp32": 1, "split_bf16": 3, "split_fp16": 3, "bf16": 1, "fp16": 1}
 ACC_FRAMES_BENCH = 16       # frames of the benchmark workload checked against the oracle
 ACC_FRAMES_SMALL = 64       # frames of the 64-element workload checked against the oracle
@@ -107,7 +111,7 @@ def source_digest() -> str:
     """SHA-256 of the fields kernel's sources: traffic counters stay valid only for this code."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hpp", "k3_factored.hpp"):
+    for name in ("kernels.hpp", "k3_factored.hpp", "k3_fft.hpp"):
         with open(os.path.join(ROOT, "paper_2412_02413_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -648,11 +652,18 @@ def main():
     def fields_roofline(r, precision):
         k3_ms = r["stage_ms"]["fields"]
         alg = fields_algorithmic_flops(geom, r["n_sel"]) * F
+        ach = alg / (k3_ms * 1e-3) / 1e12
+        if precision == "fp32":
+            # 16 x 16 FFT on the vector ALUs: no matrix-core work
+            peak = VALU_FP32_PEAK_TFLOPS
+            return {"kernel": "fields (propagator + 16 x 16 vector FFT + cross-spectra, k3fft)", "bound": "alu",
+                    "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                    "frac_of_unpacked_fp32": round(ach / VALU_FP32_UNPACKED_TFLOPS, 4),
+                    "ms": round(k3_ms, 3), "algorithmic_flops_per_launch": alg}
         exe = executed_mfma_flops(geom, r["n_sel"], F, precision)
         peak = MFMA_PEAK_TFLOPS[precision]
-        ach = alg / (k3_ms * 1e-3) / 1e12
         util = exe / (k3_ms * 1e-3) / 1e12
-        return {"kernel": "fields (propagator + two-stage DFT-GEMM + cross-spectra)", "bound": "mfma",
+        return {"kernel": "fields (propagator + two-stage DFT-GEMM + cross-spectra, k3ff)", "bound": "mfma",
                 "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                 "ms": round(k3_ms, 3), "algorithmic_flops_per_launch": alg,
                 "mfma_executed_flops_per_launch": exe, "mfma_tflops": round(util, 2),

@@ -1,0 +1,232 @@
+// K3 for FP32 operands at N = 256: the inverse lateral transform as a 16 x 16 FFT on the
+// vector ALUs.
+//
+// Same factorisation as k3_factored.hpp (q = 16 q1 + q2, x = x1 + 16 x2):
+//   stage 1  Y(x1, q2)  = sum_q1 A(16 q1 + q2) e^{2 pi i q1 x1 / 16}
+//   twiddle  Y'(x1, q2) = Y(x1, q2) e^{2 pi i q2 x1 / 256}
+//   stage 3  p(x1 + 16 x2) = sum_q2 Y'(x1, q2) e^{2 pi i q2 x2 / 16}
+// but each 16-point transform is a radix-4 x 4 FFT held in one lane's registers instead
+// of a DFT-GEMM on the matrix cores.  On gfx950 the FP32 matrix product runs at twice the
+// vector FMA rate and does not overlap vector work, while the GEMM form executes 256 flops
+// per complex output against about 11 vector operations per point and stage for the FFT,
+// so for FP32 operands the vector FFT is the faster form.  (The 16-bit forms keep the
+// matrix cores, whose rate is eight times higher and which overlap vector work.)
+//
+// Lanes: a wave holds four depths, one per group of 16 lanes (g = lane / 16), and lane j
+// of a group holds column q2 = j of stage 1 and column x1 = j of stage 3, i.e. its
+// pixels are x = j + 16 x2, x2 = 0..15.  Per bin and sub-aperture:
+//   A(16 m + j) = H G for m = 0..15 from the staged row j (K2's [q2][q1] order),
+//   16-point FFT over m, twiddle, transpose through the wave's LDS block (row x1 of its
+//   group), 16-point FFT over q2: the 16 fields of the lane's pixels.
+// The fold into the per-pixel sums is that of k3ff.  A workgroup is 4 waves = 16 depths of
+// one frame, staging each bin's coefficients and kz row in LDS (double-buffered, one
+// barrier per bin) exactly as k3ff does, so the workspace layout and K2 are shared.
+// With COH (n_sub = 1) the adjacent-pixel pair sums come from lanes j ^ 1 (column
+// partner) and g ^ 1, i.e. lane ^ 16 (depth partner).
+#pragma once
+#include "k3_factored.hpp"
+
+namespace pam {
+
+constexpr int kFtWaves = 4;                    // waves per workgroup (4 depths each)
+constexpr int kFtDepths = 4 * kFtWaves;        // depths per workgroup
+constexpr int kFtTr = 16 * kFfRow;             // float2 per lane group's transpose block [16 x1][kFfRow]
+
+// LDS: staged bins [2][ff_stage_f2], twiddles [16 x1][16 q2], transpose blocks [4 waves][4 groups][kFtTr].
+template <int NSUB>
+inline size_t k3fft_lds() {
+  return (size_t)(2 * ff_stage_f2<NSUB, 1>() + 256 + kFtWaves * 4 * kFtTr) * sizeof(float2);
+}
+
+// Two 16-byte pieces of a bin's staged inputs per thread (256 threads, (NSUB + 1) 128 <= 512
+// pieces), same element order and destinations as FfPiece<NSUB, 1>.
+template <int NSUB>
+struct FtPiece {
+  uint4 v0, v1;
+  int dst0, dst1;
+  __device__ FtPiece(int tid) {
+    dst0 = FfPiece<NSUB, 1>::where(tid);
+    dst1 = FfPiece<NSUB, 1>::where(tid + 256);
+  }
+  __device__ __forceinline__ void load(const K3Args& a, int f, int b, int tid) {
+    if (dst0 >= 0) v0 = FfPiece<NSUB, 1>::fetch(a, f, b, tid);
+    if (dst1 >= 0) v1 = FfPiece<NSUB, 1>::fetch(a, f, b, tid + 256);
+  }
+  __device__ __forceinline__ void store(float2* stage) const {
+    if (dst0 >= 0) *reinterpret_cast<uint4*>(stage + dst0) = v0;
+    if (dst1 >= 0) *reinterpret_cast<uint4*>(stage + dst1) = v1;
+  }
+};
+
+__device__ __forceinline__ float2 f2add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 f2sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 f2iadd(float2 a, float2 b) { return make_float2(a.x - b.y, a.y + b.x); }  // a + i b
+__device__ __forceinline__ float2 f2isub(float2 a, float2 b) { return make_float2(a.x + b.y, a.y - b.x); }  // a - i b
+
+// In-register inverse 16-point DFT, natural order in and out:
+//   v[k] <- sum_n v[n] e^{+2 pi i n k / 16}.
+// Radix 4 x 4 with n = 4 n1 + n2 and k = k1 + 4 k2: 4-point transforms over n1, the
+// twiddles e^{2 pi i n2 k1 / 16}, 4-point transforms over n2.  The twiddle constants are
+// cos and sin of multiples of pi / 8.
+__device__ __forceinline__ void idft16(float2 (&v)[16]) {
+  constexpr float C1 = 0.92387953251128674f;   // cos(pi / 8)
+  constexpr float S1 = 0.38268343236508977f;   // sin(pi / 8)
+  constexpr float R2 = 0.70710678118654752f;   // cos(pi / 4)
+  float2 T[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    const float2 a0 = f2add(v[n2], v[8 + n2]), a1 = f2sub(v[n2], v[8 + n2]);
+    const float2 b0 = f2add(v[4 + n2], v[12 + n2]), b1 = f2sub(v[4 + n2], v[12 + n2]);
+    T[n2][0] = f2add(a0, b0);
+    T[n2][2] = f2sub(a0, b0);
+    T[n2][1] = f2iadd(a1, b1);
+    T[n2][3] = f2isub(a1, b1);
+  }
+  // twiddles W^(n2 k1), W = e^{2 pi i / 16}
+  auto rot = [](float2 x, float c, float s) { return make_float2(x.x * c - x.y * s, x.x * s + x.y * c); };
+  T[1][1] = rot(T[1][1], C1, S1);                             // W^1
+  T[1][2] = rot(T[1][2], R2, R2);                             // W^2
+  T[1][3] = rot(T[1][3], S1, C1);                             // W^3
+  T[2][1] = rot(T[2][1], R2, R2);                             // W^2
+  T[2][2] = make_float2(-T[2][2].y, T[2][2].x);               // W^4 = i
+  T[2][3] = rot(T[2][3], -R2, R2);                            // W^6
+  T[3][1] = rot(T[3][1], S1, C1);                             // W^3
+  T[3][2] = rot(T[3][2], -R2, R2);                            // W^6
+  T[3][3] = rot(T[3][3], -C1, -S1);                           // W^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    const float2 a0 = f2add(T[0][k1], T[2][k1]), a1 = f2sub(T[0][k1], T[2][k1]);
+    const float2 b0 = f2add(T[1][k1], T[3][k1]), b1 = f2sub(T[1][k1], T[3][k1]);
+    v[k1] = f2add(a0, b0);
+    v[k1 + 8] = f2sub(a0, b0);
+    v[k1 + 4] = f2iadd(a1, b1);
+    v[k1 + 12] = f2isub(a1, b1);
+  }
+}
+
+template <int NSUB, bool COH = false>
+__global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
+  static_assert(!COH || NSUB == 1, "pair cross-spectra come with the full-aperture sums only");
+  constexpr int NP = AccCount<NSUB>::pairs;
+  extern __shared__ float2 lds_ft[];
+  float2* stage = lds_ft;                                          // [2][ff_stage_f2]
+  float2* twl = lds_ft + 2 * ff_stage_f2<NSUB, 1>();               // [16 x1][16 q2]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  float2* tr = twl + 256 + (w * 4 + g) * kFtTr;                    // this group's transpose block
+  const WgFF wg(a);
+  const int f = wg.f;
+  const int depth = wg.dt * kFtDepths + 4 * w + g;
+  const double z = depth < a.n_z ? a.z[depth] : 0.0;
+
+  // stage-1 -> stage-3 twiddles e^{2 pi i q2 x1 / 256} (the table is FP32, built in FP64)
+  for (int e = tid; e < 256; e += 256) twl[e] = a.ff_tw_vec[e];
+
+  float accS[NSUB][16];
+  float accC[NP > 0 ? NP : 1][16];
+  float accG[COH ? 4 : 1][16];
+#pragma unroll
+  for (int x2 = 0; x2 < 16; ++x2) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) accS[i][x2] = 0.f;
+#pragma unroll
+    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) accC[p][x2] = 0.f;
+#pragma unroll
+    for (int q = 0; q < (COH ? 4 : 1); ++q) accG[q][x2] = 0.f;
+  }
+
+  FtPiece<NSUB> pc(tid);
+  if (wg.b_begin < wg.b_end) {
+    pc.load(a, f, wg.b_begin, tid);
+    pc.store(stage);
+  }
+  __syncthreads();
+  for (int b = wg.b_begin; b < wg.b_end; ++b) {
+    const bool more = b + 1 < wg.b_end;
+    if (more) pc.load(a, f, b + 1, tid);
+    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB, 1>();
+    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * kFfRow) + j * kFfRow;
+    // propagator at q = 16 m + j (Eq. 2): phase in FP64 reduced to [-1/2, 1/2] cycle,
+    // hardware sin/cos; evanescent values replaced in a branch only lanes holding any take
+    float2 H[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const double ph = z * kzr[m];
+      const float r = (float)(ph - rint(ph));
+      H[m] = make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+    }
+    if (a.ev_bin[b]) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m)
+        if (kzr[m] < 0.0) H[m] = propagator(z, kzr[m], a.zero_evanescent);
+    }
+    float2 p[NSUB][16];
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) {
+      const float4* gr = reinterpret_cast<const float4*>(st + (i * 16 + j) * kFfRow);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float4 gg = gr[k];
+        p[i][2 * k] = cmul(H[2 * k], make_float2(gg.x, gg.y));
+        p[i][2 * k + 1] = cmul(H[2 * k + 1], make_float2(gg.z, gg.w));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) {
+      idft16(p[i]);                                                // Y(x1, q2 = j), x1 = 0..15
+#pragma unroll
+      for (int x1 = 0; x1 < 16; ++x1) tr[x1 * kFfRow + j] = cmul(p[i][x1], twl[x1 * 16 + j]);
+      __builtin_amdgcn_wave_barrier();
+      const float4* yr = reinterpret_cast<const float4*>(tr + j * kFfRow);   // row x1 = j
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float4 yy = yr[k];
+        p[i][2 * k] = make_float2(yy.x, yy.y);
+        p[i][2 * k + 1] = make_float2(yy.z, yy.w);
+      }
+      __builtin_amdgcn_wave_barrier();
+      idft16(p[i]);                                                // p(j + 16 x2), x2 = 0..15
+    }
+    // fold: S_i = sum |p_i|^2, C_ij = sum Re(p_i conj p_j) (Eq. 4) over the bins
+#pragma unroll
+    for (int x2 = 0; x2 < 16; ++x2) {
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i) accS[i][x2] = fmaf(p[i][x2].x, p[i][x2].x, fmaf(p[i][x2].y, p[i][x2].y, accS[i][x2]));
+      if constexpr (NSUB == 3) {
+        accC[0][x2] = fmaf(p[0][x2].x, p[1][x2].x, fmaf(p[0][x2].y, p[1][x2].y, accC[0][x2]));
+        accC[1][x2] = fmaf(p[1][x2].x, p[2][x2].x, fmaf(p[1][x2].y, p[2][x2].y, accC[1][x2]));
+        accC[2][x2] = fmaf(p[2][x2].x, p[0][x2].x, fmaf(p[2][x2].y, p[0][x2].y, accC[2][x2]));
+      } else if constexpr (NSUB == 2) {
+        accC[0][x2] = fmaf(p[0][x2].x, p[1][x2].x, fmaf(p[0][x2].y, p[1][x2].y, accC[0][x2]));
+      }
+      if constexpr (COH) {
+        const float pr = p[0][x2].x, pi = p[0][x2].y;
+        const float lr = __shfl_xor(pr, 1), li = __shfl_xor(pi, 1);
+        const float zr = __shfl_xor(pr, 16), zi = __shfl_xor(pi, 16);
+        accG[0][x2] = fmaf(pr, lr, fmaf(pi, li, accG[0][x2]));
+        accG[1][x2] = fmaf(pi, lr, fmaf(-pr, li, accG[1][x2]));
+        accG[2][x2] = fmaf(pr, zr, fmaf(pi, zi, accG[2][x2]));
+        accG[3][x2] = fmaf(pi, zr, fmaf(-pr, zi, accG[3][x2]));
+      }
+    }
+    if (more) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB, 1>());
+    __syncthreads();
+  }
+  if (depth >= a.n_z) return;
+  constexpr int NA = COH ? 5 : AccCount<NSUB>::total;
+  const size_t plane = (size_t)a.n_z * 256;
+  float* dst = a.accum + ((size_t)wg.sp * a.F + f) * NA * plane + (size_t)depth * 256 + j;
+#pragma unroll
+  for (int x2 = 0; x2 < 16; ++x2) {
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) dst[i * plane + 16 * x2] = accS[i][x2];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) dst[(NSUB + q) * plane + 16 * x2] = accC[q][x2];
+    if constexpr (COH) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[(1 + q) * plane + 16 * x2] = accG[q][x2];
+    }
+  }
+}
+
+}  // namespace pam
