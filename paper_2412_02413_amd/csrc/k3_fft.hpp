@@ -1,5 +1,5 @@
-// K3 for FP32 operands at N = 256: the inverse lateral transform as a 16 x 16 FFT on the
-// vector ALUs.
+// K3 for FP32 operands at N = 256 and 512: the inverse lateral transform as a 16 x 16 FFT
+// on the vector ALUs.
 //
 // Same factorisation as k3_factored.hpp (q = 16 q1 + q2, x = x1 + 16 x2):
 //   stage 1  Y(x1, q2)  = sum_q1 A(16 q1 + q2) e^{2 pi i q1 x1 / 16}
@@ -23,38 +23,66 @@
 // barrier per bin) exactly as k3ff does, so the workspace layout and K2 are shared.
 // With COH (n_sub = 1) the adjacent-pixel pair sums come from lanes j ^ 1 (column
 // partner) and g ^ 1, i.e. lane ^ 16 (depth partner).
+//
+// N = 512 (R = 2) splits the sum by the parity e of q as k3ff does:
+// p(x) = P_0(x mod 256) + e^{2 pi i x / 512} P_1(x mod 256), P_e the 256-point transform of
+// A(2 q' + e).  The lane groups of a wave become (depth, e) = (g / 2, g % 2), so a wave holds
+// two depths and a workgroup eight.  Lane (g, j) takes its inputs from staged row 2 j + e
+// (q = 32 m + 2 j + e, K2's order for N / 16 = 32 rows); after stage 3 the lanes g and g ^ 1
+// (lane ^ 16) exchange P_0 and P_1 of their 16 columns x' = j + 16 x2, and group e forms
+// pixel x' + 256 e as P_0 +- w P_1 with w = e^{2 pi i x' / 512} (a 16 x 16 table in LDS).
 #pragma once
 #include "k3_factored.hpp"
 
 namespace pam {
 
-constexpr int kFtWaves = 4;                    // waves per workgroup (4 depths each)
-constexpr int kFtDepths = 4 * kFtWaves;        // depths per workgroup
+constexpr int kFtWaves = 4;                    // waves per workgroup (4 / R depths each)
 constexpr int kFtTr = 16 * kFfRow;             // float2 per lane group's transpose block [16 x1][kFfRow]
 
-// LDS: staged bins [2][ff_stage_f2], twiddles [16 x1][16 q2], transpose blocks [4 waves][4 groups][kFtTr].
-template <int NSUB>
+// depths per workgroup
+template <int R>
+__host__ __device__ constexpr int ft_depths() { return 4 * kFtWaves / R; }
+
+// LDS: staged bins [2][ff_stage_f2], stage twiddles [16 x1][16 q2], (R = 2) combination
+// twiddles [16 x2][16 j], transpose blocks [4 waves][4 groups][kFtTr].
+template <int NSUB, int R = 1>
 inline size_t k3fft_lds() {
-  return (size_t)(2 * ff_stage_f2<NSUB, 1>() + 256 + kFtWaves * 4 * kFtTr) * sizeof(float2);
+  return (size_t)(2 * ff_stage_f2<NSUB, R>() + 256 * R + kFtWaves * 4 * kFtTr) * sizeof(float2);
 }
 
-// Two 16-byte pieces of a bin's staged inputs per thread (256 threads, (NSUB + 1) 128 <= 512
-// pieces), same element order and destinations as FfPiece<NSUB, 1>.
-template <int NSUB>
+// 2 R 16-byte pieces of a bin's staged inputs per thread (256 threads, (NSUB + 1) 128 R
+// <= 512 R pieces), same element order and destinations as FfPiece<NSUB, R>; separate
+// members so that they stay in registers.
+template <int NSUB, int R>
 struct FtPiece {
-  uint4 v0, v1;
-  int dst0, dst1;
+  typedef FfPiece<NSUB, R> P;
+  uint4 v0, v1, v2, v3;
+  int d0, d1, d2, d3;
   __device__ FtPiece(int tid) {
-    dst0 = FfPiece<NSUB, 1>::where(tid);
-    dst1 = FfPiece<NSUB, 1>::where(tid + 256);
+    d0 = P::where(tid);
+    d1 = P::where(tid + 256);
+    d2 = R > 1 ? P::where(tid + 512) : -1;
+    d3 = R > 1 ? P::where(tid + 768) : -1;
   }
-  __device__ __forceinline__ void load(const K3Args& a, int f, int b, int tid) {
-    if (dst0 >= 0) v0 = FfPiece<NSUB, 1>::fetch(a, f, b, tid);
-    if (dst1 >= 0) v1 = FfPiece<NSUB, 1>::fetch(a, f, b, tid + 256);
+  // pieces 0, 1 (part 0) and, at N = 512, pieces 2, 3 (part 1): the kernel moves the two
+  // parts at different points of a bin so that only two are in registers at a time
+  __device__ __forceinline__ void load(const K3Args& a, int f, int b, int tid, int part) {
+    if (part == 0) {
+      if (d0 >= 0) v0 = P::fetch(a, f, b, tid);
+      if (d1 >= 0) v1 = P::fetch(a, f, b, tid + 256);
+    } else if (R > 1) {
+      if (d2 >= 0) v2 = P::fetch(a, f, b, tid + 512);
+      if (d3 >= 0) v3 = P::fetch(a, f, b, tid + 768);
+    }
   }
-  __device__ __forceinline__ void store(float2* stage) const {
-    if (dst0 >= 0) *reinterpret_cast<uint4*>(stage + dst0) = v0;
-    if (dst1 >= 0) *reinterpret_cast<uint4*>(stage + dst1) = v1;
+  __device__ __forceinline__ void store(float2* stage, int part) const {
+    if (part == 0) {
+      if (d0 >= 0) *reinterpret_cast<uint4*>(stage + d0) = v0;
+      if (d1 >= 0) *reinterpret_cast<uint4*>(stage + d1) = v1;
+    } else if (R > 1) {
+      if (d2 >= 0) *reinterpret_cast<uint4*>(stage + d2) = v2;
+      if (d3 >= 0) *reinterpret_cast<uint4*>(stage + d3) = v3;
+    }
   }
 };
 
@@ -104,23 +132,31 @@ __device__ __forceinline__ void idft16(float2 (&v)[16]) {
   }
 }
 
-template <int NSUB, bool COH = false>
+// Two workgroups per CU (at most 256 VGPRs a lane).  At N = 512 with three sub-apertures
+// this spills a few values per bin to scratch, which measures faster (about 1.4x) than one
+// workgroup per CU without spills.
+template <int NSUB, bool COH = false, int R = 1>
 __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
-  static_assert(!COH || NSUB == 1, "pair cross-spectra come with the full-aperture sums only");
+  static_assert(!COH || (NSUB == 1 && R == 1), "pair cross-spectra come with the full-aperture sums at N = 256");
+  static_assert(R == 1 || R == 2, "N = 256 or 512");
   constexpr int NP = AccCount<NSUB>::pairs;
+  constexpr int N = 256 * R;
   extern __shared__ float2 lds_ft[];
   float2* stage = lds_ft;                                          // [2][ff_stage_f2]
-  float2* twl = lds_ft + 2 * ff_stage_f2<NSUB, 1>();               // [16 x1][16 q2]
+  float2* twl = lds_ft + 2 * ff_stage_f2<NSUB, R>();               // [16 x1][16 q2] (+ [16 x2][16 j])
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int g = lane >> 4, j = lane & 15;
-  float2* tr = twl + 256 + (w * 4 + g) * kFtTr;                    // this group's transpose block
+  const int e = R == 2 ? (g & 1) : 0;                              // parity of q (N = 512)
+  float2* tr = twl + 256 * R + (w * 4 + g) * kFtTr;                // this group's transpose block
+  const int srow = R == 1 ? j : 2 * j + e;                         // staged row of this lane's inputs
   const WgFF wg(a);
   const int f = wg.f;
-  const int depth = wg.dt * kFtDepths + 4 * w + g;
+  const int depth = R == 1 ? wg.dt * ft_depths<1>() + 4 * w + g : wg.dt * ft_depths<2>() + 2 * w + (g >> 1);
   const double z = depth < a.n_z ? a.z[depth] : 0.0;
 
-  // stage-1 -> stage-3 twiddles e^{2 pi i q2 x1 / 256} (the table is FP32, built in FP64)
-  for (int e = tid; e < 256; e += 256) twl[e] = a.ff_tw_vec[e];
+  // stage-1 -> stage-3 twiddles e^{2 pi i q2 x1 / 256} and (N = 512) the combination
+  // twiddles e^{2 pi i (j + 16 x2) / 512} (FP32 tables built in FP64)
+  for (int k = tid; k < 256 * R; k += 256) twl[k] = k < 256 ? a.ff_tw_vec[k] : a.ff_tw2_vec[k - 256];
 
   float accS[NSUB][16];
   float accC[NP > 0 ? NP : 1][16];
@@ -135,18 +171,22 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
     for (int q = 0; q < (COH ? 4 : 1); ++q) accG[q][x2] = 0.f;
   }
 
-  FtPiece<NSUB> pc(tid);
+  FtPiece<NSUB, R> pc(tid);
   if (wg.b_begin < wg.b_end) {
-    pc.load(a, f, wg.b_begin, tid);
-    pc.store(stage);
+#pragma unroll
+    for (int part = 0; part < R; ++part) {
+      pc.load(a, f, wg.b_begin, tid, part);
+      pc.store(stage, part);
+    }
   }
   __syncthreads();
   for (int b = wg.b_begin; b < wg.b_end; ++b) {
     const bool more = b + 1 < wg.b_end;
-    if (more) pc.load(a, f, b + 1, tid);
-    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB, 1>();
-    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * kFfRow) + j * kFfRow;
-    // propagator at q = 16 m + j (Eq. 2): phase in FP64 reduced to [-1/2, 1/2] cycle,
+    float2* nxt = stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB, R>();   // free since the last barrier
+    if (more) pc.load(a, f, b + 1, tid, 0);
+    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB, R>();
+    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * R * kFfRow) + srow * kFfRow;
+    // propagator at q = 16 m + j (N = 256) or 32 m + 2 j + e (N = 512) (Eq. 2): phase in FP64 reduced to [-1/2, 1/2] cycle,
     // hardware sin/cos; evanescent values replaced in a branch only lanes holding any take
     float2 H[16];
 #pragma unroll
@@ -163,7 +203,7 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
     float2 p[NSUB][16];
 #pragma unroll
     for (int i = 0; i < NSUB; ++i) {
-      const float4* gr = reinterpret_cast<const float4*>(st + (i * 16 + j) * kFfRow);
+      const float4* gr = reinterpret_cast<const float4*>(st + (i * 16 * R + srow) * kFfRow);
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const float4 gg = gr[k];
@@ -186,6 +226,20 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
       }
       __builtin_amdgcn_wave_barrier();
       idft16(p[i]);                                                // p(j + 16 x2), x2 = 0..15
+      if constexpr (R == 2) {
+        // P_0 +- w P_1: group parity e = 0 holds P_0(x'), e = 1 P_1(x'), x' = j + 16 x2
+#pragma unroll
+        for (int x2 = 0; x2 < 16; ++x2) {
+          const float2 o = make_float2(__shfl_xor(p[i][x2].x, 16), __shfl_xor(p[i][x2].y, 16));
+          const float2 p0 = e ? o : p[i][x2], p1 = e ? p[i][x2] : o;
+          const float2 t = cmul(twl[256 + x2 * 16 + j], p1);
+          p[i][x2] = e ? f2sub(p0, t) : f2add(p0, t);
+        }
+        if (i == 0 && more) {
+          pc.store(nxt, 0);
+          pc.load(a, f, b + 1, tid, 1);
+        }
+      }
     }
     // fold: S_i = sum |p_i|^2, C_ij = sum Re(p_i conj p_j) (Eq. 4) over the bins
 #pragma unroll
@@ -209,13 +263,13 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
         accG[3][x2] = fmaf(pi, zr, fmaf(-pr, zi, accG[3][x2]));
       }
     }
-    if (more) pc.store(stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB, 1>());
+    if (more) pc.store(nxt, R - 1);
     __syncthreads();
   }
   if (depth >= a.n_z) return;
   constexpr int NA = COH ? 5 : AccCount<NSUB>::total;
-  const size_t plane = (size_t)a.n_z * 256;
-  float* dst = a.accum + ((size_t)wg.sp * a.F + f) * NA * plane + (size_t)depth * 256 + j;
+  const size_t plane = (size_t)a.n_z * N;
+  float* dst = a.accum + ((size_t)wg.sp * a.F + f) * NA * plane + (size_t)depth * N + j + 256 * e;
 #pragma unroll
   for (int x2 = 0; x2 < 16; ++x2) {
 #pragma unroll

@@ -319,7 +319,8 @@ struct K3Args {
   const float2* ff_tw;     // [64 lanes][8] twiddles e^{2 pi i q2 x1 / N} of the lane's stage-1 outputs (/ 16 for FP16)
   const int32_t* ev_bin;   // [n_sel] 1 if the bin has evanescent lateral wavenumbers
   const float2* ff_tw2;    // [64 lanes][8] e^{2 pi i x' / 512} of the lane's stage-3 outputs (N = 512)
-  const float2* ff_tw_vec; // [16 x1][16 q2] e^{2 pi i q2 x1 / 256} (vector FFT kernel, N = 256)
+  const float2* ff_tw_vec; // [16 x1][16 q2] e^{2 pi i q2 x1 / 256} (vector FFT kernel)
+  const float2* ff_tw2_vec; // [16 x2][16 j] e^{2 pi i (j + 16 x2) / 512} (vector FFT kernel, N = 512)
 };
 
 template <int NSUB>

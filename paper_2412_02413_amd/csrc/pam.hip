@@ -110,7 +110,8 @@ struct pam_plan_s {
   uint16_t* d_ff_w16 = nullptr;  // [64][2][16] the same in 16-bit operand order, hi then lo per k-step
   float2* d_ff_tw = nullptr;   // [64][8] twiddles / 16 in stage-1 output order
   float2* d_ff_tw2 = nullptr;  // [64][8] N = 512 combination twiddles in stage-3 output order
-  float2* d_ff_tw_vec = nullptr;  // [16][16] stage twiddles of the vector FFT kernel (N = 256)
+  float2* d_ff_tw_vec = nullptr;  // [16][16] stage twiddles of the vector FFT kernel
+  float2* d_ff_tw2_vec = nullptr;  // [16][16] N = 512 combination twiddles of the vector FFT kernel
   // frequency-domain delay-and-sum (pam_fd_tea_tax)
   double fs = 0, c = 0;        // sampling rate, sound speed
   double dx = 0, x_first = 0;  // lateral grid spacing and coordinate of column 0
@@ -338,10 +339,13 @@ hipError_t launch_ff_r(int precision, const pam::K3Args& a, int blocks, hipStrea
 
 template <int NSUB>
 hipError_t launch_ff(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
-  // FP32 operands at N = 256: the vector FFT kernel (16 depths per workgroup, like k3ff)
+  // FP32 operands: the vector FFT kernel (16 or 8 depths per workgroup, like k3ff)
   if (precision == PAM_PREC_FP32 && a.N == 256)
     return launch_big_lds(pam::k3fft<NSUB>, pam::kFtWaves, pam::k3fft_lds<NSUB>(), pam::k3fft_lds<NSUB>(), a, blocks,
                           st);
+  if (precision == PAM_PREC_FP32 && a.N == 512)
+    return launch_big_lds(pam::k3fft<NSUB, false, 2>, pam::kFtWaves, pam::k3fft_lds<NSUB, 2>(),
+                          pam::k3fft_lds<NSUB, 2>(), a, blocks, st);
   return a.N == 512 ? launch_ff_r<NSUB, 2>(precision, a, blocks, st) : launch_ff_r<NSUB, 1>(precision, a, blocks, st);
 }
 
@@ -513,7 +517,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
   // in lane order of the matrix-core operands.  Lane l: column c = l % 32, half h = l / 32.
   std::vector<float> ff_w32;
   std::vector<uint16_t> ff_w16;
-  std::vector<float2> ff_tw, ff_tw2, ff_tw_vec;
+  std::vector<float2> ff_tw, ff_tw2, ff_tw_vec, ff_tw2_vec;
   if (p->ff) {
     auto wval = [](int row, int m, int ri) {
       const int x = row % 16, ro = row / 16;
@@ -553,6 +557,14 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
         const double th = 2.0 * kPi * (double)((q2 * x1) % 256) / 256.0;
         ff_tw_vec[x1 * 16 + q2] = make_float2((float)std::cos(th), (float)std::sin(th));
       }
+    // vector FFT kernel, N = 512: [x2][j] = e^{2 pi i (j + 16 x2) / 512}
+    ff_tw2_vec.assign(256, make_float2(0.f, 0.f));
+    if (N == 512)
+      for (int x2 = 0; x2 < 16; ++x2)
+        for (int j = 0; j < 16; ++j) {
+          const double th = 2.0 * kPi * (double)(j + 16 * x2) / 512.0;
+          ff_tw2_vec[x2 * 16 + j] = make_float2((float)std::cos(th), (float)std::sin(th));
+        }
     // stage-3 output v of lane l is x' = c % 16 + 16 (8(v/4) + 4h + v%4) of half c / 16
     ff_tw2.assign(64 * 8, make_float2(0.f, 0.f));
     if (N == 512)
@@ -575,6 +587,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       if ((st = upload(p, &p->d_ff_tw, ff_tw.data(), ff_tw.size())) != PAM_OK) break;
       if ((st = upload(p, &p->d_ff_tw2, ff_tw2.data(), ff_tw2.size())) != PAM_OK) break;
       if ((st = upload(p, &p->d_ff_tw_vec, ff_tw_vec.data(), ff_tw_vec.size())) != PAM_OK) break;
+      if ((st = upload(p, &p->d_ff_tw2_vec, ff_tw2_vec.data(), ff_tw2_vec.size())) != PAM_OK) break;
     }
     if ((st = upload(p, &p->d_z, z.data(), z.size())) != PAM_OK) break;
     if ((st = upload(p, &p->d_tw, tw.data(), tw.size())) != PAM_OK) break;
@@ -752,7 +765,7 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
     pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, accum,
                   p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent,
                   lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw, lv->d_ev, p->d_ff_tw2,
-                  p->d_ff_tw_vec};
+                  p->d_ff_tw_vec, p->d_ff_tw2_vec};
     const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
     if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
     if (launch_k3(p->precision, p->n_sub, s, a, (int)blocks, stream, p->coherence) != hipSuccess || !mark(3))
