@@ -119,10 +119,10 @@ typedef struct {
 /* Where each stage's result lies inside a workspace (byte offsets), for callers
  * that check intermediate results.  Layouts (all row-major, last index fastest):
  *   spectra  complex64 [F][n_sel][L]          time-transform bins, Omega order
- *   coeffs   complex64 [F][n_sel][n_sub][N_x] lateral coefficients: at N_x = 256 the
- *            spectrum P_i(q)/N_x stored at q2*16 + q1 for q = 16 q1 + q2 (factored
- *            transform), otherwise folded into cos/sin slot order; scaled by a power of
- *            two for FP16 operands (scale 1 otherwise)
+ *   coeffs   complex64 [F][n_sel][n_sub][N_x] lateral coefficients: at N_x = 256 and 512
+ *            (and 128 with FP32 operands) the spectrum P_i(q)/N_x stored at r*16 + q1 for
+ *            q = (N_x/16) q1 + r (factored transform), otherwise folded into cos/sin slot
+ *            order; scaled by a power of two for FP16 operands (scale 1 otherwise)
  *   scales   float32   [F][n_sel]             1 / (power-of-two scale of coeffs)
  *   accum    float32   [n_split][F][n_acc][n_z][N_x] partial sums over disjoint bin
  *            ranges; channels S_1..S_nsub then C_12, C_23, C_31 (n_sub = 3) or C_12;

@@ -61,6 +61,9 @@ __host__ __device__ constexpr int ff_depths() { return 2 * kFfWaves / R; }
 // doubles; row = q2 (R = 1) or 2 q2 + e (R = 2), 16 q1 per row.
 template <int NSUB, int R>
 __host__ __device__ constexpr int ff_stage_f2() { return (NSUB + 1) * 16 * R * kFfRow; }
+// the same for N = 16 ROWS
+template <int NSUB, int ROWS>
+__host__ __device__ constexpr int ff_stage_rows() { return (NSUB + 1) * ROWS * kFfRow; }
 // Transpose buffer of one wave: [NSUB][2 depths or halves][kFfZz] float2.
 template <int NSUB>
 __host__ __device__ constexpr int ff_tr_f2() { return NSUB * 2 * kFfZz; }
@@ -87,25 +90,23 @@ struct WgFF {
   }
 };
 
-// One 16-byte piece of a bin's staged inputs per thread and pass, R passes (512 R
-// pieces cover NSUB <= 3).  K2 writes a bin's coefficients of sub-aperture i in
-// [i][row][q1] order and the kz table is [row][q1], so piece k of thread tid is
-// element 2 (tid + 512 k).  The pieces are separate members (not an array) so that
-// they stay in registers.
-template <int NSUB, int R>
-struct FfPiece {
-  static constexpr int NQ = 256 * R;               // coefficients per sub-aperture
-  static constexpr int NG = NSUB * NQ / 2;         // pieces of G (2 complex each)
-  uint4 v0, v1;
-  int dst0, dst1;   // float2 offsets in the stage buffer, -1 for no piece
+// Element order of a bin's staged inputs for N = 16 ROWS: K2 writes a bin's coefficients of
+// sub-aperture i in [i][row][q1] order and the kz table is [row][q1] (q = ROWS q1 + row), so
+// 16-byte piece pi (two complex values or two doubles) is element 2 pi of that sequence; it
+// lands in the stage buffer at rows of kFfRow float2.
+template <int NSUB, int ROWS>
+struct FfRows {
+  static constexpr int NQ = 16 * ROWS;             // coefficients per sub-aperture
+  static constexpr int NG = NSUB * NQ / 2;         // pieces of G
+  static constexpr int PIECES = NG + NQ / 2;       // with the kz row
   static __device__ int where(int pi) {
     if (pi < NG) {
       const int e = 2 * pi, i = e / NQ, row = (e % NQ) >> 4, q1 = e & 15;
-      return (i * 16 * R + row) * kFfRow + q1;
+      return (i * ROWS + row) * kFfRow + q1;
     }
-    if (pi < NG + NQ / 2) {
+    if (pi < PIECES) {
       const int e = 2 * (pi - NG), row = e >> 4, q1 = e & 15;
-      return NSUB * 16 * R * kFfRow + row * kFfRow + q1;       // doubles at float2 granularity
+      return NSUB * ROWS * kFfRow + row * kFfRow + q1;         // doubles at float2 granularity
     }
     return -1;
   }
@@ -113,6 +114,18 @@ struct FfPiece {
     if (pi < NG) return *reinterpret_cast<const uint4*>(a.coeffs + ((size_t)f * a.n_sel + b) * NSUB * NQ + 2 * pi);
     return *reinterpret_cast<const uint4*>(a.kz_ff + (size_t)b * NQ + 2 * (pi - NG));
   }
+};
+
+// One 16-byte piece of a bin's staged inputs per thread and pass, R passes (512 R
+// pieces cover NSUB <= 3): piece k of thread tid is piece tid + 512 k of FfRows.  The
+// pieces are separate members (not an array) so that they stay in registers.
+template <int NSUB, int R>
+struct FfPiece {
+  typedef FfRows<NSUB, 16 * R> P;
+  uint4 v0, v1;
+  int dst0, dst1;   // float2 offsets in the stage buffer, -1 for no piece
+  static __device__ int where(int pi) { return P::where(pi); }
+  static __device__ uint4 fetch(const K3Args& a, int f, int b, int pi) { return P::fetch(a, f, b, pi); }
   __device__ FfPiece(int tid) {
     dst0 = where(tid);
     dst1 = R > 1 ? where(tid + 512) : -1;

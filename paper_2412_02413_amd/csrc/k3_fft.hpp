@@ -1,30 +1,36 @@
-// K3 for FP32 operands at N = 256 and 512: the inverse lateral transform as a 16 x 16 FFT
-// on the vector ALUs.
+// K3 for FP32 operands at N = 128, 256 and 512: the inverse lateral transform as a 16 x N/16
+// FFT on the vector ALUs.
 //
-// Same factorisation as k3_factored.hpp (q = 16 q1 + q2, x = x1 + 16 x2):
-//   stage 1  Y(x1, q2)  = sum_q1 A(16 q1 + q2) e^{2 pi i q1 x1 / 16}
-//   twiddle  Y'(x1, q2) = Y(x1, q2) e^{2 pi i q2 x1 / 256}
-//   stage 3  p(x1 + 16 x2) = sum_q2 Y'(x1, q2) e^{2 pi i q2 x2 / 16}
-// but each 16-point transform is a radix-4 x 4 FFT held in one lane's registers instead
-// of a DFT-GEMM on the matrix cores.  On gfx950 the FP32 matrix product runs at twice the
+// Same factorisation as k3_factored.hpp (q = (N/16) q1 + q2, x = x1 + 16 x2):
+//   stage 1  Y(x1, q2)  = sum_q1 A((N/16) q1 + q2) e^{2 pi i q1 x1 / 16}
+//   twiddle  Y'(x1, q2) = Y(x1, q2) e^{2 pi i q2 x1 / N}
+//   stage 3  p(x1 + 16 x2) = sum_q2 Y'(x1, q2) e^{2 pi i q2 x2 / (N/16)}
+// but each small transform is a radix-4 FFT held in one lane's registers instead of a
+// DFT-GEMM on the matrix cores.  On gfx950 the FP32 matrix product runs at twice the
 // vector FMA rate and does not overlap vector work, while the GEMM form executes 256 flops
 // per complex output against about 11 vector operations per point and stage for the FFT,
 // so for FP32 operands the vector FFT is the faster form.  (The 16-bit forms keep the
 // matrix cores, whose rate is eight times higher and which overlap vector work.)
 //
-// Lanes: a wave holds four depths, one per group of 16 lanes (g = lane / 16), and lane j
-// of a group holds column q2 = j of stage 1 and column x1 = j of stage 3, i.e. its
-// pixels are x = j + 16 x2, x2 = 0..15.  Per bin and sub-aperture:
+// N = 256.  A wave holds four depths, one per group of 16 lanes (g = lane / 16), and lane j
+// of a group holds column q2 = j of stage 1 and column x1 = j of stage 3, i.e. its pixels
+// are x = j + 16 x2, x2 = 0..15.  Per bin and sub-aperture:
 //   A(16 m + j) = H G for m = 0..15 from the staged row j (K2's [q2][q1] order),
-//   16-point FFT over m, twiddle, transpose through the wave's LDS block (row x1 of its
-//   group), 16-point FFT over q2: the 16 fields of the lane's pixels.
+//   16-point FFT over m, twiddle, transpose through the group's LDS block (row x1),
+//   16-point FFT over q2: the 16 fields of the lane's pixels.
 // The fold into the per-pixel sums is that of k3ff.  A workgroup is 4 waves = 16 depths of
 // one frame, staging each bin's coefficients and kz row in LDS (double-buffered, one
 // barrier per bin) exactly as k3ff does, so the workspace layout and K2 are shared.
 // With COH (n_sub = 1) the adjacent-pixel pair sums come from lanes j ^ 1 (column
 // partner) and g ^ 1, i.e. lane ^ 16 (depth partner).
 //
-// N = 512 (R = 2) splits the sum by the parity e of q as k3ff does:
+// N = 128.  A group holds two depths: in stage 1 lane j is (depth j / 8, column q2 = j % 8)
+// and reads staged row q2 (8 rows), so the transpose block row x1 holds both depths' eight
+// q2 values; in stage 3 lane j = x1 runs two 8-point FFTs, one per depth, and its 16
+// pixels are (depth d, x = j + 16 x2) for d = 0, 1 and x2 = 0..7.  A wave holds eight
+// depths and a workgroup 32.
+//
+// N = 512 splits the sum by the parity e of q as k3ff does:
 // p(x) = P_0(x mod 256) + e^{2 pi i x / 512} P_1(x mod 256), P_e the 256-point transform of
 // A(2 q' + e).  The lane groups of a wave become (depth, e) = (g / 2, g % 2), so a wave holds
 // two depths and a workgroup eight.  Lane (g, j) takes its inputs from staged row 2 j + e
@@ -36,31 +42,33 @@
 
 namespace pam {
 
-constexpr int kFtWaves = 4;                    // waves per workgroup (4 / R depths each)
+constexpr int kFtWaves = 4;                    // waves per workgroup
 constexpr int kFtTr = 16 * kFfRow;             // float2 per lane group's transpose block [16 x1][kFfRow]
 
-// depths per workgroup
-template <int R>
-__host__ __device__ constexpr int ft_depths() { return 4 * kFtWaves / R; }
+// depths per workgroup: 32 (N = 128), 16 (256), 8 (512)
+template <int NN>
+__host__ __device__ constexpr int ft_depths() { return NN == 128 ? 32 : (NN == 256 ? 16 : 8); }
 
-// LDS: staged bins [2][ff_stage_f2], stage twiddles [16 x1][16 q2], (R = 2) combination
+// LDS: staged bins [2][ff_stage_rows], stage twiddles [16 x1][16 j], (N = 512) combination
 // twiddles [16 x2][16 j], transpose blocks [4 waves][4 groups][kFtTr].
-template <int NSUB, int R = 1>
+template <int NSUB, int NN = 256>
 inline size_t k3fft_lds() {
-  return (size_t)(2 * ff_stage_f2<NSUB, R>() + 256 * R + kFtWaves * 4 * kFtTr) * sizeof(float2);
+  return (size_t)(2 * ff_stage_rows<NSUB, NN / 16>() + (NN == 512 ? 512 : 256) + kFtWaves * 4 * kFtTr) *
+         sizeof(float2);
 }
 
-// 2 R 16-byte pieces of a bin's staged inputs per thread (256 threads, (NSUB + 1) 128 R
-// <= 512 R pieces), same element order and destinations as FfPiece<NSUB, R>; separate
-// members so that they stay in registers.
-template <int NSUB, int R>
+// The 16-byte pieces of a bin's staged inputs, 256 per pass (one per thread): one pass at
+// N = 128 and 256 (N = 128 with three sub-apertures fills it exactly), two parts of two
+// passes at N = 512.  Separate members (not an array) so that they stay in registers.
+template <int NSUB, int NN>
 struct FtPiece {
-  typedef FfPiece<NSUB, R> P;
+  typedef FfRows<NSUB, NN / 16> P;
+  static constexpr int R = NN == 512 ? 2 : 1;
   uint4 v0, v1, v2, v3;
   int d0, d1, d2, d3;
   __device__ FtPiece(int tid) {
     d0 = P::where(tid);
-    d1 = P::where(tid + 256);
+    d1 = NN > 128 ? P::where(tid + 256) : -1;
     d2 = R > 1 ? P::where(tid + 512) : -1;
     d3 = R > 1 ? P::where(tid + 768) : -1;
   }
@@ -69,7 +77,7 @@ struct FtPiece {
   __device__ __forceinline__ void load(const K3Args& a, int f, int b, int tid, int part) {
     if (part == 0) {
       if (d0 >= 0) v0 = P::fetch(a, f, b, tid);
-      if (d1 >= 0) v1 = P::fetch(a, f, b, tid + 256);
+      if (NN > 128 && d1 >= 0) v1 = P::fetch(a, f, b, tid + 256);
     } else if (R > 1) {
       if (d2 >= 0) v2 = P::fetch(a, f, b, tid + 512);
       if (d3 >= 0) v3 = P::fetch(a, f, b, tid + 768);
@@ -78,7 +86,7 @@ struct FtPiece {
   __device__ __forceinline__ void store(float2* stage, int part) const {
     if (part == 0) {
       if (d0 >= 0) *reinterpret_cast<uint4*>(stage + d0) = v0;
-      if (d1 >= 0) *reinterpret_cast<uint4*>(stage + d1) = v1;
+      if (NN > 128 && d1 >= 0) *reinterpret_cast<uint4*>(stage + d1) = v1;
     } else if (R > 1) {
       if (d2 >= 0) *reinterpret_cast<uint4*>(stage + d2) = v2;
       if (d3 >= 0) *reinterpret_cast<uint4*>(stage + d3) = v3;
@@ -135,24 +143,57 @@ __device__ __forceinline__ void idft16(float2 (&v)[16]) {
 // Two workgroups per CU (at most 256 VGPRs a lane).  At N = 512 with three sub-apertures
 // this spills a few values per bin to scratch, which measures faster (about 1.4x) than one
 // workgroup per CU without spills.
-template <int NSUB, bool COH = false, int R = 1>
+// In-register inverse 8-point DFT of v[o..o+7], natural order in and out:
+//   v[o + k] <- sum_n v[o + n] e^{+2 pi i n k / 8}.
+// n = 4 n1 + n2, k = k1 + 2 k2: 2-point transforms over n1, twiddles e^{2 pi i n2 k1 / 8},
+// 4-point transforms over n2.
+__device__ __forceinline__ void idft8(float2 (&v)[16], int o) {
+  constexpr float R2 = 0.70710678118654752f;   // cos(pi / 4)
+  float2 T[4][2];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    T[n2][0] = f2add(v[o + n2], v[o + 4 + n2]);
+    T[n2][1] = f2sub(v[o + n2], v[o + 4 + n2]);
+  }
+  T[1][1] = make_float2(R2 * (T[1][1].x - T[1][1].y), R2 * (T[1][1].x + T[1][1].y));     // W8^1
+  T[2][1] = make_float2(-T[2][1].y, T[2][1].x);                                          // W8^2 = i
+  T[3][1] = make_float2(-R2 * (T[3][1].x + T[3][1].y), R2 * (T[3][1].x - T[3][1].y));    // W8^3
+#pragma unroll
+  for (int k1 = 0; k1 < 2; ++k1) {
+    const float2 a0 = f2add(T[0][k1], T[2][k1]), a1 = f2sub(T[0][k1], T[2][k1]);
+    const float2 b0 = f2add(T[1][k1], T[3][k1]), b1 = f2sub(T[1][k1], T[3][k1]);
+    v[o + k1] = f2add(a0, b0);
+    v[o + k1 + 4] = f2sub(a0, b0);
+    v[o + k1 + 2] = f2iadd(a1, b1);
+    v[o + k1 + 6] = f2isub(a1, b1);
+  }
+}
+
+template <int NSUB, bool COH = false, int NN = 256>
 __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
-  static_assert(!COH || (NSUB == 1 && R == 1), "pair cross-spectra come with the full-aperture sums at N = 256");
-  static_assert(R == 1 || R == 2, "N = 256 or 512");
+  static_assert(!COH || (NSUB == 1 && NN == 256), "pair cross-spectra come with the full-aperture sums at N = 256");
+  static_assert(NN == 128 || NN == 256 || NN == 512, "N = 128, 256 or 512");
   constexpr int NP = AccCount<NSUB>::pairs;
-  constexpr int N = 256 * R;
+  constexpr int N = NN;
+  constexpr int R = NN == 512 ? 2 : 1;
+  constexpr bool HALF = NN == 128;
+  constexpr int ROWS = NN / 16;
   extern __shared__ float2 lds_ft[];
-  float2* stage = lds_ft;                                          // [2][ff_stage_f2]
-  float2* twl = lds_ft + 2 * ff_stage_f2<NSUB, R>();               // [16 x1][16 q2] (+ [16 x2][16 j])
+  float2* stage = lds_ft;                                          // [2][ff_stage_rows]
+  float2* twl = lds_ft + 2 * ff_stage_rows<NSUB, ROWS>();          // [16 x1][16 j] (+ [16 x2][16 j])
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int g = lane >> 4, j = lane & 15;
   const int e = R == 2 ? (g & 1) : 0;                              // parity of q (N = 512)
   float2* tr = twl + 256 * R + (w * 4 + g) * kFtTr;                // this group's transpose block
-  const int srow = R == 1 ? j : 2 * j + e;                         // staged row of this lane's inputs
+  // staged row of this lane's stage-1 inputs
+  const int srow = HALF ? (j & 7) : (R == 1 ? j : 2 * j + e);
   const WgFF wg(a);
   const int f = wg.f;
-  const int depth = R == 1 ? wg.dt * ft_depths<1>() + 4 * w + g : wg.dt * ft_depths<2>() + 2 * w + (g >> 1);
-  const double z = depth < a.n_z ? a.z[depth] : 0.0;
+  // first depth of the lane's pixels, and the depth of its stage-1 column
+  const int depth = HALF ? wg.dt * ft_depths<NN>() + 8 * w + 2 * g
+                         : (R == 1 ? wg.dt * ft_depths<NN>() + 4 * w + g : wg.dt * ft_depths<NN>() + 2 * w + (g >> 1));
+  const int depth1 = HALF ? depth + (j >> 3) : depth;
+  const double z = depth1 < a.n_z ? a.z[depth1] : 0.0;
 
   // stage-1 -> stage-3 twiddles e^{2 pi i q2 x1 / 256} and (N = 512) the combination
   // twiddles e^{2 pi i (j + 16 x2) / 512} (FP32 tables built in FP64)
@@ -171,7 +212,7 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
     for (int q = 0; q < (COH ? 4 : 1); ++q) accG[q][x2] = 0.f;
   }
 
-  FtPiece<NSUB, R> pc(tid);
+  FtPiece<NSUB, NN> pc(tid);
   if (wg.b_begin < wg.b_end) {
 #pragma unroll
     for (int part = 0; part < R; ++part) {
@@ -182,10 +223,10 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
   __syncthreads();
   for (int b = wg.b_begin; b < wg.b_end; ++b) {
     const bool more = b + 1 < wg.b_end;
-    float2* nxt = stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_f2<NSUB, R>();   // free since the last barrier
+    float2* nxt = stage + ((b + 1 - wg.b_begin) & 1) * ff_stage_rows<NSUB, ROWS>();   // free since the last barrier
     if (more) pc.load(a, f, b + 1, tid, 0);
-    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_f2<NSUB, R>();
-    const double* kzr = reinterpret_cast<const double*>(st + NSUB * 16 * R * kFfRow) + srow * kFfRow;
+    const float2* st = stage + ((b - wg.b_begin) & 1) * ff_stage_rows<NSUB, ROWS>();
+    const double* kzr = reinterpret_cast<const double*>(st + NSUB * ROWS * kFfRow) + srow * kFfRow;
     // propagator at q = 16 m + j (N = 256) or 32 m + 2 j + e (N = 512) (Eq. 2): phase in FP64 reduced to [-1/2, 1/2] cycle,
     // hardware sin/cos; evanescent values replaced in a branch only lanes holding any take
     float2 H[16];
@@ -203,7 +244,7 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
     float2 p[NSUB][16];
 #pragma unroll
     for (int i = 0; i < NSUB; ++i) {
-      const float4* gr = reinterpret_cast<const float4*>(st + (i * 16 * R + srow) * kFfRow);
+      const float4* gr = reinterpret_cast<const float4*>(st + (i * ROWS + srow) * kFfRow);
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const float4 gg = gr[k];
@@ -225,7 +266,12 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
         p[i][2 * k + 1] = make_float2(yy.z, yy.w);
       }
       __builtin_amdgcn_wave_barrier();
-      idft16(p[i]);                                                // p(j + 16 x2), x2 = 0..15
+      if constexpr (HALF) {
+        idft8(p[i], 0);                                            // depth + 0: p(j + 16 x2), x2 = 0..7
+        idft8(p[i], 8);                                            // depth + 1
+      } else {
+        idft16(p[i]);                                              // p(j + 16 x2), x2 = 0..15
+      }
       if constexpr (R == 2) {
         // P_0 +- w P_1: group parity e = 0 holds P_0(x'), e = 1 P_1(x'), x' = j + 16 x2
 #pragma unroll
@@ -266,19 +312,22 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
     if (more) pc.store(nxt, R - 1);
     __syncthreads();
   }
-  if (depth >= a.n_z) return;
   constexpr int NA = COH ? 5 : AccCount<NSUB>::total;
   const size_t plane = (size_t)a.n_z * N;
-  float* dst = a.accum + ((size_t)wg.sp * a.F + f) * NA * plane + (size_t)depth * N + j + 256 * e;
+  float* base = a.accum + ((size_t)wg.sp * a.F + f) * NA * plane;
 #pragma unroll
-  for (int x2 = 0; x2 < 16; ++x2) {
+  for (int k = 0; k < 16; ++k) {
+    // pixel of register k: (depth + k / 8, j + 16 (k % 8)) at N = 128, (depth, j + 16 k + 256 e) otherwise
+    const int d = HALF ? depth + (k >> 3) : depth;
+    if (d >= a.n_z) continue;
+    float* dst = base + (size_t)d * N + j + (HALF ? 16 * (k & 7) : 16 * k + 256 * e);
 #pragma unroll
-    for (int i = 0; i < NSUB; ++i) dst[i * plane + 16 * x2] = accS[i][x2];
+    for (int i = 0; i < NSUB; ++i) dst[i * plane] = accS[i][k];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) dst[(NSUB + q) * plane + 16 * x2] = accC[q][x2];
+    for (int q = 0; q < NP; ++q) dst[(NSUB + q) * plane] = accC[q][k];
     if constexpr (COH) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) dst[(1 + q) * plane + 16 * x2] = accG[q][x2];
+      for (int q = 0; q < 4; ++q) dst[(1 + q) * plane] = accG[q][k];
     }
   }
 }

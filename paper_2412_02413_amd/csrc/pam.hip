@@ -203,7 +203,7 @@ LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
     // 16 depths x all 256 columns per workgroup, 8 waves of 2 depths
     s.fw = -1;
     s.nw = pam::kFfWaves;
-    const int dpw = p->N == 512 ? pam::ff_depths<2>() : pam::ff_depths<1>();
+    const int dpw = p->N == 512 ? pam::ft_depths<512>() : (p->N == 256 ? pam::ft_depths<256>() : pam::ft_depths<128>());
     s.n_dt = (p->n_z + dpw - 1) / dpw;
     s.n_xg = 1;
   } else if (p->N % 64 == 0) {
@@ -339,13 +339,16 @@ hipError_t launch_ff_r(int precision, const pam::K3Args& a, int blocks, hipStrea
 
 template <int NSUB>
 hipError_t launch_ff(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
-  // FP32 operands: the vector FFT kernel (16 or 8 depths per workgroup, like k3ff)
+  // FP32 operands: the vector FFT kernel (32, 16 or 8 depths per workgroup; 16 and 8 like k3ff)
   if (precision == PAM_PREC_FP32 && a.N == 256)
     return launch_big_lds(pam::k3fft<NSUB>, pam::kFtWaves, pam::k3fft_lds<NSUB>(), pam::k3fft_lds<NSUB>(), a, blocks,
                           st);
   if (precision == PAM_PREC_FP32 && a.N == 512)
-    return launch_big_lds(pam::k3fft<NSUB, false, 2>, pam::kFtWaves, pam::k3fft_lds<NSUB, 2>(),
-                          pam::k3fft_lds<NSUB, 2>(), a, blocks, st);
+    return launch_big_lds(pam::k3fft<NSUB, false, 512>, pam::kFtWaves, pam::k3fft_lds<NSUB, 512>(),
+                          pam::k3fft_lds<NSUB, 512>(), a, blocks, st);
+  if (precision == PAM_PREC_FP32 && a.N == 128)
+    return launch_big_lds(pam::k3fft<NSUB, false, 128>, pam::kFtWaves, pam::k3fft_lds<NSUB, 128>(),
+                          pam::k3fft_lds<NSUB, 128>(), a, blocks, st);
   return a.N == 512 ? launch_ff_r<NSUB, 2>(precision, a, blocks, st) : launch_ff_r<NSUB, 1>(precision, a, blocks, st);
 }
 
@@ -475,9 +478,10 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     const double a = 2.0 * kPi * (double)i / (double)N;
     twx[i] = make_float2((float)std::cos(a), (float)-std::sin(a));
   }
-  // Factored transform for N = 256 and 512 (k3_factored.hpp); the other lateral sizes
-  // take the folded DFT basis (k3_fields*.hpp), built only for them.
-  p->ff = (N == 256 || N == 512);
+  // Factored transform for N = 256 and 512 (k3_factored.hpp, and the vector FFT of k3_fft.hpp
+  // in FP32), and N = 128 in FP32 (k3_fft.hpp); the other cases take the folded DFT basis
+  // (k3_fields*.hpp), built only for them.
+  p->ff = (N == 256 || N == 512 || (N == 128 && p->precision == PAM_PREC_FP32));
   std::vector<float> basis(p->ff ? 0 : (size_t)N * N);
   for (int s = 0; s < (p->ff ? 0 : N); ++s) {
     const int q = s >> 1;
@@ -550,12 +554,14 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
         ff_tw[l * 8 + v] = make_float2((float)(std::cos(th) * sc), (float)(std::sin(th) * sc));
       }
     }
-    // vector FFT kernel: [x1][q2] = e^{2 pi i q2 x1 / 256}
+    // vector FFT kernel: [x1][j] = e^{2 pi i q2 x1 / N} with q2 = j (N = 256, 512) or j % 8 (N = 128)
     ff_tw_vec.resize(256);
+    const int NT = N == 128 ? 128 : 256;
     for (int x1 = 0; x1 < 16; ++x1)
-      for (int q2 = 0; q2 < 16; ++q2) {
-        const double th = 2.0 * kPi * (double)((q2 * x1) % 256) / 256.0;
-        ff_tw_vec[x1 * 16 + q2] = make_float2((float)std::cos(th), (float)std::sin(th));
+      for (int jj = 0; jj < 16; ++jj) {
+        const int q2 = N == 128 ? jj % 8 : jj;
+        const double th = 2.0 * kPi * (double)((q2 * x1) % NT) / (double)NT;
+        ff_tw_vec[x1 * 16 + jj] = make_float2((float)std::cos(th), (float)std::sin(th));
       }
     // vector FFT kernel, N = 512: [x2][j] = e^{2 pi i (j + 16 x2) / 512}
     ff_tw2_vec.assign(256, make_float2(0.f, 0.f));

@@ -301,15 +301,22 @@ def test_shipped_calibration_on_benchmark_frames(env):
     rf = torch.from_numpy(S.generate_rf(list(range(6_000_000, 6_000_032)), 0, "headline")).cuda()
     pipe = S.SurrogatePipeline(g, net, tau=cal["tau"], max_frames=32)
     teacher = S.Teacher(g, max_frames=32)
+    fb_t = None
     try:
         image, mask, est, fb = pipe(rf)
         _, plain = teacher(rf)
+        plain = plain.clone()
+        fb_t = torch.as_tensor(np.nonzero(fb)[0], device="cuda")
+        # the pipeline recomputes its fallback frames as one smaller batch: the same call
+        # reproduces them bit for bit (a different batch size changes the bin split and so
+        # the FP32 summation order)
+        _, plain_fb = teacher(rf.index_select(0, fb_t).contiguous()) if len(fb_t) else (None, None)
         torch.cuda.synchronize()
     finally:
         pipe.close()
         teacher.close()
-    fb_t = torch.as_tensor(fb, device="cuda")
-    assert torch.equal(image[fb_t], plain[fb_t])
+    if len(fb_t):
+        assert torch.equal(image.index_select(0, fb_t), plain_fb)
     err = ((image - plain).flatten(1).norm(dim=1) / plain.flatten(1).norm(dim=1)).cpu().numpy()
     over = (~fb) & (err > cal["bound"])
     print(f"fallback {fb.mean():.3f}, accepted over the bound {over.mean():.3f}, accepted error "
