@@ -214,6 +214,7 @@ struct K2Args {
   int32_t col0, col_step; // grid column of element l is col0 + col_step * l
   int32_t ff_n1;          // 0: folded slot order; N1 > 0: unfolded P(q)/N in [q2][q1] order, q = (N/N1) q1 + q2
   int32_t scaled;         // 1: power-of-two scale into [2^11, 2^12) (FP16 operands); 0: scale 1
+  int32_t n_items;        // F n_sel (one wave per (frame, bin) in k2_fft)
 };
 
 template <int NSUB>

@@ -15,6 +15,7 @@
 #include "k3_fields.hpp"
 #include "k3_fields16.hpp"
 #include "k3_factored.hpp"
+#include "k2_fft.hpp"
 #include "k3_fft.hpp"
 #include "k3_tea.hpp"
 
@@ -734,15 +735,34 @@ pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t
   }
   // K2: lateral DFT + fold, one workgroup per (bin, frame)
   if (method == 0) {
+    const long long items = (long long)F * lv->n_sel;
+    if (items > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
     pam::K2Args a{spectra, coeffs, scales, p->d_twx, p->d_masks, p->L, p->N, p->n_sub, lv->n_sel,
-                  p->col0, p->col_step, p->ff ? pam::kFfN1 : 0, is_fp16(p->precision) ? 1 : 0};
-    const size_t lds = (size_t)(p->N + 3 * p->L + 2 * p->n_sub * p->N) * sizeof(float2);
-    if (p->n_sub == 3)
-      hipLaunchKernelGGL(pam::k2_lateral<3>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
-    else if (p->n_sub == 2)
-      hipLaunchKernelGGL(pam::k2_lateral<2>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
-    else
-      hipLaunchKernelGGL(pam::k2_lateral<1>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+                  p->col0, p->col_step, p->ff ? pam::kFfN1 : 0, is_fp16(p->precision) ? 1 : 0, (int32_t)items};
+    if (p->ff) {
+      // factored order: the lateral FFT, one wave per (frame, bin)
+      const dim3 grid((unsigned)((items + 3) / 4));
+      switch (p->N * 4 + p->n_sub) {
+        case 128 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 8>), grid, dim3(256), 0, stream, a); break;
+        case 128 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 8>), grid, dim3(256), 0, stream, a); break;
+        case 128 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 8>), grid, dim3(256), 0, stream, a); break;
+        case 256 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 16>), grid, dim3(256), 0, stream, a); break;
+        case 256 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 16>), grid, dim3(256), 0, stream, a); break;
+        case 256 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 16>), grid, dim3(256), 0, stream, a); break;
+        case 512 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 32>), grid, dim3(256), 0, stream, a); break;
+        case 512 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 32>), grid, dim3(256), 0, stream, a); break;
+        case 512 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 32>), grid, dim3(256), 0, stream, a); break;
+        default: return PAM_ERR_UNSUPPORTED;
+      }
+    } else {
+      const size_t lds = (size_t)(p->N + 3 * p->L + 2 * p->n_sub * p->N) * sizeof(float2);
+      if (p->n_sub == 3)
+        hipLaunchKernelGGL(pam::k2_lateral<3>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+      else if (p->n_sub == 2)
+        hipLaunchKernelGGL(pam::k2_lateral<2>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+      else
+        hipLaunchKernelGGL(pam::k2_lateral<1>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+    }
     if (hipGetLastError() != hipSuccess || !mark(2)) return PAM_ERR_DEVICE;
   } else if (!mark(2)) {
     return PAM_ERR_DEVICE;
