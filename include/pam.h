@@ -33,7 +33,10 @@
  *   device tables.  pam_as_tax never allocates device memory: all scratch
  *   space is the caller's workspace.  Every argument is validated before any
  *   work is enqueued; on error nothing is enqueued and no output is written.
- *   Device faults surface at the caller's next synchronisation of the stream.
+ *   Device faults surface at the caller's next synchronisation of the stream.  A
+ *   PAM_ERR_DEVICE from a launch after validation (a HIP runtime failure) can leave the
+ *   earlier stages of that call enqueued; their results are then incomplete and the
+ *   outputs must not be used.
  *   A plan is immutable after creation: concurrent pam_as_tax calls on one
  *   plan are safe when they use different streams and different workspaces.
  */
@@ -220,6 +223,16 @@ pam_status_t pam_as_tax_noalloc(pam_plan_t p, const float* rf, int64_t n_frames,
 void pam_destroy(pam_plan_t p);
 
 const char* pam_status_string(pam_status_t s);
+
+/* Test hooks for the error paths (callers: test suites).
+ * pam_debug_fail_allocation(n): the n-th next device allocation made while building a
+ *   plan (n = 0: the next one) fails as if the device were out of memory, so pam_plan
+ *   returns PAM_ERR_OOM after releasing what it had allocated; n < 0 disarms.  One
+ *   injected failure per call; not meant for use beside concurrent pam_plan calls.
+ * pam_debug_live_allocations(): the number of device allocations held by all live plans
+ *   of the process (a leak check: unchanged across a failed pam_plan). */
+void pam_debug_fail_allocation(int32_t n);
+int64_t pam_debug_live_allocations(void);
 
 #ifdef __cplusplus
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -123,9 +124,17 @@ struct pam_plan_s {
 
 namespace {
 
+// allocation-failure injection for tests (pam_debug_fail_allocation) and the count of
+// device allocations the library's plans hold (pam_debug_live_allocations)
+std::atomic<int> g_fail_alloc{-1};
+std::atomic<long long> g_live_allocs{0};
+
 void free_plan(pam_plan_s* p) {
   if (!p) return;
-  for (void* q : p->allocs) (void)hipFree(q);
+  for (void* q : p->allocs) {
+    (void)hipFree(q);
+    --g_live_allocs;
+  }
   delete p;
 }
 
@@ -133,8 +142,13 @@ template <typename T>
 pam_status_t upload(pam_plan_s* p, T** dst, const T* src, size_t n) {
   void* ptr = nullptr;
   const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  int armed = g_fail_alloc.load();
+  while (armed >= 0 && !g_fail_alloc.compare_exchange_weak(armed, armed - 1)) {
+  }
+  if (armed == 0) return PAM_ERR_OOM;  // injected failure (the counter is now disarmed)
   if (hipMalloc(&ptr, bytes) != hipSuccess) return PAM_ERR_OOM;
   p->allocs.push_back(ptr);
+  ++g_live_allocs;
   if (n && hipMemcpy(ptr, src, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return PAM_ERR_DEVICE;
   *dst = static_cast<T*>(ptr);
   return PAM_OK;
@@ -835,6 +849,10 @@ pam_status_t pam_fd_tea_tax(pam_plan_t p, const float* rf, int64_t n_frames, int
 }
 
 void pam_destroy(pam_plan_t p) { free_plan(p); }
+
+void pam_debug_fail_allocation(int32_t n) { g_fail_alloc.store(n < 0 ? -1 : n); }
+
+int64_t pam_debug_live_allocations(void) { return g_live_allocs.load(); }
 
 }  // extern "C"
 

@@ -87,6 +87,10 @@ def _lib():
         lib.pam_destroy.restype = None
         lib.pam_status_string.argtypes = [C.c_int]
         lib.pam_status_string.restype = C.c_char_p
+        lib.pam_debug_fail_allocation.argtypes = [i32]
+        lib.pam_debug_fail_allocation.restype = None
+        lib.pam_debug_live_allocations.argtypes = []
+        lib.pam_debug_live_allocations.restype = i64
         _LIB = lib
     return _LIB
 
@@ -160,6 +164,16 @@ def pam_plan(geom, device: int = 0, precision: str = "fp32") -> Plan:
     _check(_lib().pam_plan_get_info(h, C.byref(info)), "pam_plan_get_info")
     del keep
     return Plan(h.value, geom, precision, info)
+
+
+def debug_fail_allocation(n: int) -> None:
+    """Make the n-th next device allocation of plan building fail as out of memory (n < 0 disarms)."""
+    _lib().pam_debug_fail_allocation(n)
+
+
+def debug_live_allocations() -> int:
+    """Device allocations held by all live plans of the process."""
+    return int(_lib().pam_debug_live_allocations())
 
 
 def pam_destroy(plan: Plan) -> None:

@@ -396,16 +396,19 @@ def features(A, feats, energy, fmax):
 # ----------------------------------------------------------------------------
 
 def train(net: UNet, A, R, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 0, log=None, log_every=50,
-          mix: float = 0.1):
+          mix: float = 0.1, rng: Optional[np.random.Generator] = None):
     """Adam on batches drawn from (A, R); the loss weights each pixel by its share of the
-    frame's energy (blended with a uniform share `mix`), where the mask shapes the image."""
+    frame's energy (blended with a uniform share `mix`), where the mask shapes the image.
+    The batches come from `rng` (advanced in place, so a run resumes from a checkpoint of
+    the network, its Adam state and rng.bit_generator.state) or a fresh generator seeded
+    with `seed`."""
     torch = net.torch
     n, _, H, W = A.shape
     feats = torch.empty((batch, H, W, C_FEAT), dtype=torch.bfloat16, device=net.device)
     e = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
     wts = torch.empty((batch, H, W), dtype=torch.float32, device=net.device)
     fmax = torch.empty(batch, dtype=torch.float32, device=net.device)
-    rng = np.random.default_rng(seed)
+    rng = np.random.default_rng(seed) if rng is None else rng
     hist = []
     t0 = time.perf_counter()
     for it in range(steps):

@@ -441,3 +441,34 @@ def test_factored_512_forms(pam, torch_cuda, precision, n_sub):
     tol_i, tol_rho = {"fp32": (TOL_I, TOL_RHO), "bf16": (1e-2, 5e-2)}.get(precision, SPLIT_TOL)
     for f in range(2):
         check_end_to_end(res, O.as_tax(rf[f], g), f, tol_i=tol_i, tol_rho=tol_rho)
+
+
+def test_injected_allocation_failure_leaks_nothing(pam, torch_cuda):
+    """An out-of-memory at any point of plan building returns PAM_ERR_OOM and releases every
+    table the plan had allocated (checked by the library's live-allocation count)."""
+    g = synth.cfg1_geometry()
+    base = pam.debug_live_allocations()
+    plan = pam.pam_plan(g, 0, "fp32")
+    n_allocs = pam.debug_live_allocations() - base
+    pam.pam_destroy(plan)
+    assert n_allocs > 5 and pam.debug_live_allocations() == base
+    try:
+        for k in sorted({0, 1, 2, n_allocs // 2, n_allocs - 1}):
+            pam.debug_fail_allocation(k)
+            with pytest.raises(pam.PamError) as err:
+                pam.pam_plan(g, 0, "fp32")
+            assert err.value.status == -2           # PAM_ERR_OOM
+            assert pam.debug_live_allocations() == base
+        # past the last allocation the injection never fires: the plan builds and still works
+        pam.debug_fail_allocation(n_allocs + 5)
+        plan = pam.pam_plan(g, 0, "fp32")
+    finally:
+        pam.debug_fail_allocation(-1)
+    try:
+        rf = synth.cfg1_frame(9)
+        res = pam.reconstruct(plan, torch_cuda.from_numpy(rf[None]).cuda())
+        torch_cuda.cuda.synchronize()
+        assert np.isfinite(res["image"].cpu().numpy()).all()
+    finally:
+        pam.pam_destroy(plan)
+    assert pam.debug_live_allocations() == base

@@ -323,3 +323,32 @@ def test_shipped_calibration_on_benchmark_frames(env):
           f"max {err[~fb].max() if (~fb).any() else 0:.3f}", flush=True)
     assert np.all((est.cpu().numpy() > cal["tau"]) == fb)
     assert over.mean() <= cal["alpha"] + 0.1
+
+
+def test_resumed_training_follows_the_same_trajectory(env, small_data):
+    """A run checkpointed after 4 steps (master weights, Adam moments and step, the batch
+    sampler's generator state) and resumed in a fresh network retraces the next 4 losses and
+    ends at the same parameters.  The weight gradients sum with atomics, so the agreement
+    is to FP32 rounding, not bit for bit."""
+    import copy
+    torch, nn, S = env
+    g, A, R, _, _ = small_data
+    net = S.UNet(3, 32, seed=5)
+    rng = np.random.default_rng(11)
+    S.train(net, A, R, steps=4, batch=4, lr=3e-4, rng=rng, log_every=1)
+    ck = {k: (v.clone() if torch.is_tensor(v) else v) for k, v in net.state_dict().items()}
+    state = copy.deepcopy(rng.bit_generator.state)
+    h1 = S.train(net, A, R, steps=4, batch=4, lr=3e-4, rng=rng, log_every=1)
+    other = S.UNet(3, 32, seed=99)
+    other.load_state_dict(ck)
+    rng2 = np.random.default_rng(0)
+    rng2.bit_generator.state = state
+    h2 = S.train(other, A, R, steps=4, batch=4, lr=3e-4, rng=rng2, log_every=1)
+    assert [h[0] for h in h1] == [h[0] for h in h2]
+    for a, b in zip(h1, h2):
+        for x, y in zip(a[1:], b[1:]):
+            assert abs(x - y) <= 1e-4 * max(abs(x), 1e-6), (a, b)
+    assert other.step_count == net.step_count == 8
+    for k in net.params:
+        d = (net.params[k] - other.params[k]).abs().max().item()
+        assert d <= 1e-4 * max(net.params[k].abs().max().item(), 1e-6), k
