@@ -290,41 +290,59 @@ def run_frames(pam, torch, geom, rf_np, precision, dev):
 
 def mixed_lengths(pam, torch, precisions, steps, dev):
     """64 frames of the 64-element array with record lengths drawn from 2048/4096/8192 on one
-    8192-sample plan: one launch per record length on one stream (the bins of a record are
-    every 2nd / 4th bin of the plan's), timed over all 64 frames."""
+    8192-sample plan (the bins of a record are every 2nd / 4th bin of the plan's), timed over
+    all 64 frames as ONE grouped call (pam_as_tax_grouped: the frames packed by record length,
+    the fields stage one work-list launch on the factored kernels) and, for comparison, as
+    one pam_as_tax call per record length."""
     from paper_2412_02413_amd import synth
     g = synth.cfg3_geometry()
     frames = [synth.cfg3_frame(s) for s in range(64)]
     lengths = sorted({fr.shape[-1] for fr in frames})
     groups = {n: [i for i, fr in enumerate(frames) if fr.shape[-1] == n] for n in lengths}
+    glist = [(n, len(groups[n])) for n in lengths]
     dev_rf = {n: torch.from_numpy(np.stack([frames[i] for i in idx])).to(dev) for n, idx in groups.items()}
-    out = {"frames": 64, "record_lengths": {str(n): len(idx) for n, idx in groups.items()}}
+    packed = torch.cat([dev_rf[n].reshape(-1) for n in lengths]).contiguous()
+    out = {"frames": 64, "record_lengths": {str(n): len(idx) for n, idx in groups.items()},
+           "call": "one pam_as_tax_grouped call per 64 frames (frames packed by record length)"}
     firsts = {}
     for prec in precisions:
         plan = pam.pam_plan(g, 0, prec)
         try:
             stream = torch.cuda.current_stream(dev)
+            img = torch.empty((64, g.n_z, g.n_x), device=dev)
+            nn = torch.empty_like(img)
+            ws = pam.alloc_workspace_grouped(plan, glist, dev)
             bufs = {}
             for n, x in dev_rf.items():
                 F = x.shape[0]
                 bufs[n] = (torch.empty((F, g.n_z, g.n_x), device=dev), torch.empty((F, g.n_z, g.n_x), device=dev),
                            pam.alloc_workspace(plan, F, n, dev))
 
-            def step():
-                for n, x in dev_rf.items():
-                    img, nn, ws = bufs[n]
-                    pam.pam_as_tax(plan, x, img, nn, None, ws, stream, n)
+            def grouped():
+                pam.pam_as_tax_grouped(plan, packed, glist, img, nn, None, ws, stream)
 
-            step()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                step()
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            out[prec] = {"frames_per_s": round(64 * steps / wall, 2), "ms_per_64_frames": round(1e3 * wall / steps, 3)}
-            firsts[prec] = {n: (bufs[n][0][0].cpu().numpy().astype(np.float64),
-                                bufs[n][1][0].cpu().numpy().astype(np.float64)) for n in groups}
+            def per_length():
+                for n, x in dev_rf.items():
+                    im, nc, w = bufs[n]
+                    pam.pam_as_tax(plan, x, im, nc, None, w, stream, n)
+
+            res = {}
+            for name, fn in (("grouped", grouped), ("per_length_calls", per_length)):
+                fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    fn()
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                res[name] = {"frames_per_s": round(64 * steps / wall, 2), "ms_per_64_frames": round(1e3 * wall / steps, 3)}
+            out[prec] = {**res["grouped"], "per_length_calls": res["per_length_calls"]}
+            # first frame of each record length, from the grouped call (packed order)
+            k, fr = 0, {}
+            for n in lengths:
+                fr[n] = (img[k].cpu().numpy().astype(np.float64), nn[k].cpu().numpy().astype(np.float64))
+                k += len(groups[n])
+            firsts[prec] = fr
         finally:
             pam.pam_destroy(plan)
     return out, firsts, groups

@@ -128,7 +128,7 @@ typedef struct {
  *            order; scaled by a power of two for FP16 operands (scale 1 otherwise)
  *   scales   float32   [F][n_sel]             1 / (power-of-two scale of coeffs)
  *   accum    float32   [n_split][F][n_acc][n_z][N_x] partial sums over disjoint bin
- *            ranges; channels S_1..S_nsub then C_12, C_23, C_31 (n_sub = 3) or C_12;
+ *            ranges (the region reserves room beyond n_split F planes); channels S_1..S_nsub then C_12, C_23, C_31 (n_sub = 3) or C_12;
  *            with coherence (n_sub = 1): S, then Re and Im of the lateral pair sum
  *            G_x(z, x) = sum_w p(z, x) conj(p(z, x ^ 1)) and of the axial pair sum
  *            G_z(z, x) = sum_w p(z, x) conj(p(z ^ 1, x)) (pairs of adjacent columns 2j, 2j+1
@@ -154,7 +154,13 @@ pam_status_t pam_plan_get_bins(pam_plan_t p, int32_t* bins, int32_t capacity);
 
 /* Workspace bytes and stage layout for n_frames frames of n_t samples each.
  * n_t must be n_samples / 2^j (j >= 0) and >= 32; such a record uses the plan
- * bins whose frequency lies on its own grid (every 2^j-th bin k). */
+ * bins whose frequency lies on its own grid (every 2^j-th bin k).  The size never
+ * shrinks as n_frames or n_t grows, so a workspace sized for n frames of n_t samples
+ * serves every call of at most n frames of at most n_t samples.  The fields stage
+ * splits each frame's bins into n_split ranges (chosen per call from the frames, the
+ * bins and how many fields workgroups the device holds at once); the accum region
+ * reserves n_frames plus a fixed number of spare planes, enough for any split the
+ * library picks. */
 pam_status_t pam_workspace_size(pam_plan_t p, int64_t n_frames, int32_t n_t, size_t* bytes);
 pam_status_t pam_workspace_layout(pam_plan_t p, int64_t n_frames, int32_t n_t,
                                   pam_workspace_layout_t* layout);
@@ -199,9 +205,10 @@ pam_status_t pam_fd_tea_tax(pam_plan_t p, const float* rf, int64_t n_frames, int
                             float* image, float* nncc, float* rho_pairs,
                             void* workspace, size_t ws_bytes, void* hip_stream);
 
-/* Bytes of the library's built-in device scratch used by pam_as_tax_noalloc (64 MiB:
- * one frame of 128 elements x 4096 samples x 768 bins on a 512 x 256 grid needs 54 MB). */
-#define PAM_NOALLOC_SCRATCH_BYTES (64u << 20)
+/* Bytes of the library's built-in device scratch used by pam_as_tax_noalloc (128 MiB:
+ * one frame of 128 elements x 4096 samples x 768 bins on a 512 x 256 grid needs about
+ * 110 MB, most of it the partial-sum planes of the bin split). */
+#define PAM_NOALLOC_SCRATCH_BYTES (128u << 20)
 
 /* pam_as_tax without a caller workspace and without any allocation, for callers that
  * cannot allocate device memory (work captured into a HIP graph, tight serving loops,
@@ -218,6 +225,30 @@ pam_status_t pam_fd_tea_tax(pam_plan_t p, const float* rf, int64_t n_frames, int
  *   value a kernel reads was written earlier in the same call. */
 pam_status_t pam_as_tax_noalloc(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t,
                                 float* image, float* nncc, float* rho_pairs, void* hip_stream);
+
+/* Frames of different record lengths in one call (the ragged batches of Section II-E's
+ * record lengths: every record on its own time-frequency grid, all on one plan).
+ * groups[g] = {n_t, n_frames}: group g holds n_frames records of n_t samples (each n_t one
+ * of the plan's record lengths, as for pam_as_tax; 1 <= n_groups <= 8, at most 65535 frames
+ * in all).  rf (device) holds the groups back to back, group g as
+ * [n_frames][L][n_t] after the groups before it; image, nncc (and rho_pairs) hold the
+ * frames in the same order.  The workspace (pam_workspace_size_grouped bytes, 256-byte
+ * aligned) holds the groups' workspaces back to back, each laid out as
+ * pam_workspace_layout would for that group with the bin split chosen over the whole
+ * call where the fields stage is one launch (else per group); it serves any group list whose groups, position by position, have no more
+ * frames and no longer records.  Stages K1, K2 and K4 run per group; on the factored fields kernels (N_x = 256 or
+ * 512, and 128 with FP32 operands) the fields stage runs as one launch over all groups
+ * (a grouped work list), otherwise per group.  Results equal pam_as_tax on each group up
+ * to FP32 summation order (the bin split depends on the frames of the call).  Errors as
+ * pam_as_tax; PAM_ERR_INVALID_ARG for a bad group list. */
+typedef struct {
+  int32_t n_t;       /* record length of the group's frames */
+  int64_t n_frames;  /* frames in the group (may be 0) */
+} pam_group_t;
+pam_status_t pam_workspace_size_grouped(pam_plan_t p, const pam_group_t* groups, int32_t n_groups, size_t* bytes);
+pam_status_t pam_as_tax_grouped(pam_plan_t p, const float* rf, const pam_group_t* groups, int32_t n_groups,
+                                float* image, float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes,
+                                void* hip_stream);
 
 /* Release the plan's device tables.  NULL-safe; no work may be in flight. */
 void pam_destroy(pam_plan_t p);

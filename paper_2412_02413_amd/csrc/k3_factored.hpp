@@ -72,16 +72,13 @@ inline size_t k3ff_lds() {
   return (size_t)(2 * ff_stage_f2<NSUB, R>() + kFfWaves * ff_tr_f2<NSUB>()) * sizeof(float2);
 }
 
-// Workgroup index -> (frame, depth tile, bin split).  Consecutive workgroups are
-// dispatched round-robin over the 8 XCDs; the remap gives each XCD a contiguous
-// range of logical indices, so the workgroups of one frame (which read the same
-// per-bin coefficients) share one L2.
+// Logical workgroup index (wg_group: XCD remap, group-local) -> (frame, depth tile, bin
+// split).  Consecutive workgroups are dispatched round-robin over the 8 XCDs; the remap
+// gives each XCD a contiguous range of logical indices, so the workgroups of one frame
+// (which read the same per-bin coefficients) share one L2.
 struct WgFF {
   int sp, dt, f, b_begin, b_end;
-  __device__ WgFF(const K3Args& a) {
-    const int G = gridDim.x;
-    int bid = blockIdx.x;
-    if ((G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
+  __device__ WgFF(const K3Args& a, int bid) {
     sp = bid % a.n_split; bid /= a.n_split;
     dt = bid % a.n_dt;    bid /= a.n_dt;
     f = bid;
@@ -242,7 +239,7 @@ struct FfOps {
 // with its lateral pair partner (column x ^ 1, the adjacent lane) and its axial pair
 // partner (depth 2i <-> 2i + 1, the lane 16 away), G = sum over bins of p conj(p').
 template <typename T, int PASSES, int NSUB, bool COH = false, int R = 1>
-__global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
+__global__ __launch_bounds__(512, 1) void k3ff(K3Args a0, K3Groups grp) {
   static_assert(!COH || (NSUB == 1 && R == 1), "pair cross-spectra come with the full-aperture sums at N = 256");
   static_assert(R == 1 || R == 2, "N = 256 or 512");
   constexpr bool F32 = std::is_same<T, float>::value;
@@ -253,7 +250,8 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a) {
   float2* stage = lds2;                                          // [2][ff_stage_f2<NSUB, R>]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   float2* tr = lds2 + 2 * ff_stage_f2<NSUB, R>() + w * ff_tr_f2<NSUB>();
-  const WgFF wg(a);
+  K3Args a = a0;
+  const WgFF wg(a, wg_group(a, grp));
   const int f = wg.f;
   const int c = lane & 31, h = lane >> 5;
   // stage-1 column (q2, zz), stage-3 column (x1, zz): zz is the depth (N = 256) or the

@@ -170,7 +170,7 @@ __device__ __forceinline__ void idft8(float2 (&v)[16], int o) {
 }
 
 template <int NSUB, bool COH = false, int NN = 256>
-__global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
+__global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
   static_assert(!COH || (NSUB == 1 && NN == 256), "pair cross-spectra come with the full-aperture sums at N = 256");
   static_assert(NN == 128 || NN == 256 || NN == 512, "N = 128, 256 or 512");
   constexpr int NP = AccCount<NSUB>::pairs;
@@ -187,7 +187,8 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a) {
   float2* tr = twl + 256 * R + (w * 4 + g) * kFtTr;                // this group's transpose block
   // staged row of this lane's stage-1 inputs
   const int srow = HALF ? (j & 7) : (R == 1 ? j : 2 * j + e);
-  const WgFF wg(a);
+  K3Args a = a0;
+  const WgFF wg(a, wg_group(a, grp));
   const int f = wg.f;
   // first depth of the lane's pixels, and the depth of its stage-1 column
   const int depth = HALF ? wg.dt * ft_depths<NN>() + 8 * w + 2 * g

@@ -324,6 +324,48 @@ struct K3Args {
   const float2* ff_tw2_vec; // [16 x2][16 j] e^{2 pi i (j + 16 x2) / 512} (vector FFT kernel, N = 512)
 };
 
+// Grouped work list of the factored fields kernels: frames of different record lengths
+// (different bin sets) in one launch.  Group g owns workgroups [wg_begin, next wg_begin);
+// its frames, bins and bin split replace the batch fields of K3Args.  n = 0: one batch.
+constexpr int kMaxGroups = 8;
+struct K3Group {
+  const float2* coeffs;
+  const float* inv_scale;
+  const double* kz_ff;
+  const int32_t* ev_bin;
+  float* accum;
+  int32_t wg_begin, F, n_sel, n_split, bins_per_split;
+};
+struct K3Groups {
+  int32_t n;
+  K3Group g[kMaxGroups];
+};
+
+// Workgroup index after the XCD remap (the workgroups of one logical range run on one XCD,
+// so those of a frame share its L2); for a grouped launch the group's fields are patched
+// into `a` and the index is made group-local.
+__device__ __forceinline__ int wg_group(K3Args& a, const K3Groups& grp) {
+  const int G = gridDim.x;
+  int bid = blockIdx.x;
+  if ((G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
+  if (grp.n > 0) {
+    int g = 0;
+    while (g + 1 < grp.n && bid >= grp.g[g + 1].wg_begin) ++g;
+    const K3Group& q = grp.g[g];
+    a.coeffs = q.coeffs;
+    a.inv_scale = q.inv_scale;
+    a.kz_ff = q.kz_ff;
+    a.ev_bin = q.ev_bin;
+    a.accum = q.accum;
+    a.F = q.F;
+    a.n_sel = q.n_sel;
+    a.n_split = q.n_split;
+    a.bins_per_split = q.bins_per_split;
+    bid -= q.wg_begin;
+  }
+  return bid;
+}
+
 template <int NSUB>
 struct AccCount {
   static constexpr int pairs = NSUB == 3 ? 3 : (NSUB == 2 ? 1 : 0);

@@ -119,6 +119,7 @@ struct pam_plan_s {
   double dx = 0, x_first = 0;  // lateral grid spacing and coordinate of column 0
   double xl_first = 0, pitch = 0;  // coordinate of element 0 and element pitch
   int32_t* d_subs = nullptr;   // [L] bit i set if sub-aperture i holds element l
+  int k3_slots = 512;          // K3 workgroups resident on the device at once
   std::vector<void*> allocs;
 };
 
@@ -209,13 +210,14 @@ struct LaunchShape {
   int fw;   // < 0: the factored two-stage kernel (N = 256, 512)
 };
 
-LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
+// Workgroup tiling of one frame: depth tiles x column groups, before any bin split.
+LaunchShape k3_tiles(const pam_plan_s* p) {
   LaunchShape s;
   s.xt = 1;
   s.ct = 0;
   s.fw = 0;
   if (p->ff) {
-    // 16 depths x all 256 columns per workgroup, 8 waves of 2 depths
+    // all columns per workgroup, ft_depths (vector FFT) depths per workgroup
     s.fw = -1;
     s.nw = pam::kFfWaves;
     const int dpw = p->N == 512 ? pam::ft_depths<512>() : (p->N == 256 ? pam::ft_depths<256>() : pam::ft_depths<128>());
@@ -234,19 +236,78 @@ LaunchShape k3_shape(const pam_plan_s* p, int64_t F, int n_sel) {
     s.nw = (tiles % 4 == 0) ? 4 : (tiles % 2 == 0 ? 2 : 1);
     s.n_xg = p->N / (32 * s.nw * s.xt);
   }
-  const int64_t base = F * s.n_dt * s.n_xg;
-  int split = 1;
-  if (base > 0 && base < 512) {
-    split = (int)((512 + base - 1) / base);
-    split = std::min(split, std::max(1, n_sel / 8));
+  s.n_split = 1;
+  s.bins_per_split = 0;
+  return s;
+}
+
+int n_acc(int n_sub, int coherence = 0) { return n_sub == 3 ? 6 : (n_sub == 2 ? 3 : (coherence ? 5 : 1)); }
+
+// Partial-sum planes a group's workspace holds beyond one per frame: room for two rounds of
+// extra workgroups.  A group of F frames splits its bins at most 1 + spare / F ways, so its
+// accumulator region (F + spare planes) and with it the workspace size never shrink as F
+// grows: a workspace sized for F frames serves every call of fewer frames.
+int64_t k3_spare_planes(const pam_plan_s* p) {
+  const LaunchShape t = k3_tiles(p);
+  const int64_t tiles = (int64_t)t.n_dt * t.n_xg;
+  return (2 * (int64_t)std::max(1, p->k3_slots) + tiles - 1) / tiles;
+}
+
+// The bin split of a K3 launch over n groups of frames (F[g] frames of n_sel[g] bins).
+// A frame is tiles = n_dt n_xg workgroups; splitting its bins s ways makes s workgroups of
+// ceil(n_sel / s) bins each, whose partial sums K4 adds.  The device holds p->k3_slots
+// workgroups at once, so near-equal workgroups run in rounds: n workgroups of at most b bins
+// take about ceil(n / slots) (b + c) bin-times, c (two bins) standing for a workgroup's
+// start and its partial-sum write, and every split beyond the first costs K4 one more
+// partial-sum plane per frame (n_acc pix floats, read at about 4 TB/s against about 5 us
+// per bin).  Returns the bins-per-workgroup cap b (every group splits into ceil(n_sel / b)
+// parts) that minimises the estimate, the largest such b on ties, at least 8 bins (or the
+// widest band when narrower), among the caps whose splits fit the spare planes.
+int k3_bin_cap(const pam_plan_s* p, const int64_t* F, const int* n_sel, int n) {
+  const LaunchShape t = k3_tiles(p);
+  const int64_t tiles = (int64_t)t.n_dt * t.n_xg;
+  const int64_t spare = k3_spare_planes(p);
+  int max_n = 0;
+  for (int g = 0; g < n; ++g) max_n = std::max(max_n, n_sel[g]);
+  if (max_n == 0) return 1;
+  const double slots = std::max(1, p->k3_slots);
+  const double plane_cost = (double)n_acc(p->n_sub, p->coherence) * p->n_z * p->N * 4.0 / 4e12 / 5e-6;
+  double best = 0;
+  int best_b = max_n;
+  for (int b = max_n; b >= std::min(8, max_n); --b) {
+    int64_t n_wg = 0;
+    int job = 0;
+    double k4 = 0;
+    bool fits = true;
+    for (int g = 0; g < n; ++g) {
+      if (F[g] == 0 || n_sel[g] == 0) continue;
+      const int split = (n_sel[g] + b - 1) / b;
+      fits = fits && (int64_t)(split - 1) * F[g] <= spare;
+      n_wg += F[g] * tiles * split;
+      job = std::max(job, (n_sel[g] + split - 1) / split);
+      k4 += plane_cost * (double)F[g] * (split - 1);
+    }
+    if (!fits) break;                      // smaller caps split further still
+    const double cost = std::ceil((double)n_wg / slots) * (job + 2.0) + k4;
+    if (b == max_n || cost < best - 1e-9) {
+      best = cost;
+      best_b = b;
+    }
   }
-  split = std::max(1, std::min(split, std::max(1, n_sel)));
-  s.bins_per_split = (n_sel + split - 1) / split;
-  s.n_split = (n_sel + s.bins_per_split - 1) / s.bins_per_split;
+  return best_b;
+}
+
+// The launch shape of one group: its tiling, and its bins split under the cap b.
+LaunchShape k3_shape(const pam_plan_s* p, int n_sel, int b) {
+  LaunchShape s = k3_tiles(p);
   if (n_sel == 0) {
     s.n_split = 1;
     s.bins_per_split = 0;
+    return s;
   }
+  const int split = (n_sel + b - 1) / b;
+  s.bins_per_split = (n_sel + split - 1) / split;
+  s.n_split = (n_sel + s.bins_per_split - 1) / s.bins_per_split;
   return s;
 }
 
@@ -256,12 +317,12 @@ const Level* level_for(const pam_plan_s* p, int n_t) {
   return nullptr;
 }
 
-int n_acc(int n_sub, int coherence = 0) { return n_sub == 3 ? 6 : (n_sub == 2 ? 3 : (coherence ? 5 : 1)); }
-
-pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layout_t* out) {
+// bin_cap: the bins-per-workgroup cap of the launch this group is part of (-1: the group alone)
+pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layout_t* out, int bin_cap = -1) {
   const Level* lv = level_for(p, n_t);
   if (!lv) return PAM_ERR_INVALID_ARG;
-  const LaunchShape s = k3_shape(p, F, lv->n_sel);
+  if (bin_cap < 0) bin_cap = k3_bin_cap(p, &F, &lv->n_sel, 1);
+  const LaunchShape s = k3_shape(p, lv->n_sel, bin_cap);
   const size_t pix = (size_t)p->n_z * p->N;
   const size_t n_blk = (pix + 255) / 256;
   pam_workspace_layout_t L{};
@@ -269,7 +330,8 @@ pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layou
   L.spectra = o;  o = align256(o + (size_t)F * lv->n_sel * p->L * sizeof(float2));
   L.coeffs = o;   o = align256(o + (size_t)F * lv->n_sel * p->n_sub * p->N * sizeof(float2));
   L.scales = o;   o = align256(o + (size_t)F * lv->n_sel * sizeof(float));
-  L.accum = o;    o = align256(o + (size_t)s.n_split * F * n_acc(p->n_sub, p->coherence) * pix * sizeof(float));
+  const size_t planes = F > 0 ? (size_t)F + (size_t)k3_spare_planes(p) : 0;   // >= n_split F
+  L.accum = o;    o = align256(o + planes * n_acc(p->n_sub, p->coherence) * pix * sizeof(float));
   L.energy = o;   o = align256(o + (size_t)F * pix * sizeof(float));
   L.weight = o;   o = align256(o + (size_t)F * pix * sizeof(float));
   L.blockmax = o; o = align256(o + (size_t)F * n_blk * sizeof(float));
@@ -281,21 +343,30 @@ pam_status_t layout(const pam_plan_s* p, int64_t F, int n_t, pam_workspace_layou
   return PAM_OK;
 }
 
+// Where a K3 dispatch goes: a launch on stream st, or, with occ set, no launch but the
+// number of the kernel's workgroups one CU holds (written to *occ).
+struct Target {
+  hipStream_t st;
+  int* occ;
+};
+
 // K3 kernels: NC consumer + NC producer waves, NC*32 columns per workgroup.
 // LDS above 64 KiB needs the per-kernel attribute.
 // (Every kernel shares one signature, so the attribute is set per launch rather
 // than cached in a per-instantiation static.)
 template <typename K>
-hipError_t launch_with_lds(K kernel, int nc, size_t lds, const pam::K3Args& a, int blocks, hipStream_t st) {
+hipError_t launch_with_lds(K kernel, int nc, size_t lds, const pam::K3Args& a, int blocks, Target st) {
   const hipError_t attr =
       hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(nc * 128), lds, st, a);
+  if (st.occ)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(st.occ, reinterpret_cast<const void*>(kernel), nc * 128, lds);
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(nc * 128), lds, st.st, a);
   return hipGetLastError();
 }
 
 template <int NSUB, int NC>
-hipError_t launch_prec(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+hipError_t launch_prec(int precision, const pam::K3Args& a, int blocks, Target st) {
   switch (precision) {
     case PAM_PREC_SPLIT_BF16:
       return launch_with_lds(pam::k3_fields_split<__bf16, 3, NSUB, NC>, NC, pam::k3_split_lds<3, NSUB, NC>(), a, blocks, st);
@@ -311,7 +382,7 @@ hipError_t launch_prec(int precision, const pam::K3Args& a, int blocks, hipStrea
 }
 
 template <int NSUB, int CT>
-hipError_t launch_prec16(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+hipError_t launch_prec16(int precision, const pam::K3Args& a, int blocks, Target st) {
   switch (precision) {
     case PAM_PREC_SPLIT_BF16:
       return launch_with_lds(pam::k3f16_split<__bf16, 3, NSUB, CT>, 4, pam::k3f16_split_lds<3, NSUB, CT>(), a, blocks, st);
@@ -329,47 +400,52 @@ hipError_t launch_prec16(int precision, const pam::K3Args& a, int blocks, hipStr
 // Kernels with more than 64 KB of dynamic LDS: the attribute is set before each launch
 // for the largest size the instantiation takes.
 template <typename K>
-hipError_t launch_big_lds(K kernel, int nw, size_t lds, size_t lds_max, const pam::K3Args& a, int blocks,
-                        hipStream_t st) {
+hipError_t launch_big_lds(K kernel, int nw, size_t lds, size_t lds_max, const pam::K3Args& a,
+                          const pam::K3Groups& grp, int blocks, Target st) {
   const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
   if (attr != hipSuccess) return attr;
   if (lds > lds_max) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(nw * 64), lds, st, a);
+  if (st.occ)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(st.occ, reinterpret_cast<const void*>(kernel), nw * 64, lds);
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(nw * 64), lds, st.st, a, grp);
   return hipGetLastError();
 }
 
 template <int NSUB, int R>
-hipError_t launch_ff_r(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+hipError_t launch_ff_r(int precision, const pam::K3Args& a, const pam::K3Groups& grp, int blocks, Target st) {
   using namespace pam;
   const size_t lds = k3ff_lds<NSUB, R>();
   switch (precision) {
-    case PAM_PREC_SPLIT_BF16: return launch_big_lds(k3ff<__bf16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_SPLIT_FP16: return launch_big_lds(k3ff<_Float16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_BF16: return launch_big_lds(k3ff<__bf16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
-    case PAM_PREC_FP16: return launch_big_lds(k3ff<_Float16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
-    default: return launch_big_lds(k3ff<float, 1, NSUB, false, R>, kFfWaves, lds, lds, a, blocks, st);
+    case PAM_PREC_SPLIT_BF16: return launch_big_lds(k3ff<__bf16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, grp, blocks, st);
+    case PAM_PREC_SPLIT_FP16: return launch_big_lds(k3ff<_Float16, 3, NSUB, false, R>, kFfWaves, lds, lds, a, grp, blocks, st);
+    case PAM_PREC_BF16: return launch_big_lds(k3ff<__bf16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, grp, blocks, st);
+    case PAM_PREC_FP16: return launch_big_lds(k3ff<_Float16, 1, NSUB, false, R>, kFfWaves, lds, lds, a, grp, blocks, st);
+    default: return launch_big_lds(k3ff<float, 1, NSUB, false, R>, kFfWaves, lds, lds, a, grp, blocks, st);
   }
 }
 
 template <int NSUB>
-hipError_t launch_ff(int precision, const pam::K3Args& a, int blocks, hipStream_t st) {
+hipError_t launch_ff(int precision, const pam::K3Args& a, const pam::K3Groups& grp, int blocks, Target st) {
   // FP32 operands: the vector FFT kernel (32, 16 or 8 depths per workgroup; 16 and 8 like k3ff)
   if (precision == PAM_PREC_FP32 && a.N == 256)
-    return launch_big_lds(pam::k3fft<NSUB>, pam::kFtWaves, pam::k3fft_lds<NSUB>(), pam::k3fft_lds<NSUB>(), a, blocks,
-                          st);
+    return launch_big_lds(pam::k3fft<NSUB>, pam::kFtWaves, pam::k3fft_lds<NSUB>(), pam::k3fft_lds<NSUB>(), a, grp,
+                          blocks, st);
   if (precision == PAM_PREC_FP32 && a.N == 512)
     return launch_big_lds(pam::k3fft<NSUB, false, 512>, pam::kFtWaves, pam::k3fft_lds<NSUB, 512>(),
-                          pam::k3fft_lds<NSUB, 512>(), a, blocks, st);
+                          pam::k3fft_lds<NSUB, 512>(), a, grp, blocks, st);
   if (precision == PAM_PREC_FP32 && a.N == 128)
     return launch_big_lds(pam::k3fft<NSUB, false, 128>, pam::kFtWaves, pam::k3fft_lds<NSUB, 128>(),
-                          pam::k3fft_lds<NSUB, 128>(), a, blocks, st);
-  return a.N == 512 ? launch_ff_r<NSUB, 2>(precision, a, blocks, st) : launch_ff_r<NSUB, 1>(precision, a, blocks, st);
+                          pam::k3fft_lds<NSUB, 128>(), a, grp, blocks, st);
+  return a.N == 512 ? launch_ff_r<NSUB, 2>(precision, a, grp, blocks, st)
+                    : launch_ff_r<NSUB, 1>(precision, a, grp, blocks, st);
 }
 
 template <int NSUB>
-hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& a, int blocks, hipStream_t st) {
-  if (s.fw < 0) return launch_ff<NSUB>(precision, a, blocks, st);
+hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& a, const pam::K3Groups& grp,
+                        int blocks, Target st) {
+  if (s.fw < 0) return launch_ff<NSUB>(precision, a, grp, blocks, st);
+  if (grp.n > 0) return hipErrorInvalidValue;      // grouped work lists run on the factored kernels only
   if (s.ct == 4) return launch_prec16<NSUB, 4>(precision, a, blocks, st);
   if (s.ct == 2) return launch_prec16<NSUB, 2>(precision, a, blocks, st);
   if (s.ct == 1) return launch_prec16<NSUB, 1>(precision, a, blocks, st);
@@ -378,23 +454,23 @@ hipError_t launch_shape(int precision, const LaunchShape& s, const pam::K3Args& 
   return launch_prec<NSUB, 1>(precision, a, blocks, st);
 }
 
-hipError_t launch_k3(int precision, int n_sub, const LaunchShape& s, const pam::K3Args& a, int blocks,
-                     hipStream_t st, int coherence) {
+hipError_t launch_k3(int precision, int n_sub, const LaunchShape& s, const pam::K3Args& a, const pam::K3Groups& grp,
+                     int blocks, Target st, int coherence) {
   if (coherence) {
     using namespace pam;
     const size_t lds = k3ff_lds<1>();
     switch (precision) {
-      case PAM_PREC_SPLIT_BF16: return launch_big_lds(k3ff<__bf16, 3, 1, true>, kFfWaves, lds, lds, a, blocks, st);
-      case PAM_PREC_SPLIT_FP16: return launch_big_lds(k3ff<_Float16, 3, 1, true>, kFfWaves, lds, lds, a, blocks, st);
-      case PAM_PREC_BF16: return launch_big_lds(k3ff<__bf16, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
-      case PAM_PREC_FP16: return launch_big_lds(k3ff<_Float16, 1, 1, true>, kFfWaves, lds, lds, a, blocks, st);
-      default: return launch_big_lds(k3fft<1, true>, kFtWaves, k3fft_lds<1>(), k3fft_lds<1>(), a, blocks, st);
+      case PAM_PREC_SPLIT_BF16: return launch_big_lds(k3ff<__bf16, 3, 1, true>, kFfWaves, lds, lds, a, grp, blocks, st);
+      case PAM_PREC_SPLIT_FP16: return launch_big_lds(k3ff<_Float16, 3, 1, true>, kFfWaves, lds, lds, a, grp, blocks, st);
+      case PAM_PREC_BF16: return launch_big_lds(k3ff<__bf16, 1, 1, true>, kFfWaves, lds, lds, a, grp, blocks, st);
+      case PAM_PREC_FP16: return launch_big_lds(k3ff<_Float16, 1, 1, true>, kFfWaves, lds, lds, a, grp, blocks, st);
+      default: return launch_big_lds(k3fft<1, true>, kFtWaves, k3fft_lds<1>(), k3fft_lds<1>(), a, grp, blocks, st);
     }
   }
   switch (n_sub) {
-    case 3: return launch_shape<3>(precision, s, a, blocks, st);
-    case 2: return launch_shape<2>(precision, s, a, blocks, st);
-    default: return launch_shape<1>(precision, s, a, blocks, st);
+    case 3: return launch_shape<3>(precision, s, a, grp, blocks, st);
+    case 2: return launch_shape<2>(precision, s, a, grp, blocks, st);
+    default: return launch_shape<1>(precision, s, a, grp, blocks, st);
   }
 }
 
@@ -661,6 +737,21 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
     free_plan(p);
     return st;
   }
+  // the K3 workgroups the device holds at once: the bin split plans its launches in rounds of these
+  {
+    pam::K3Args a{};
+    a.N = p->N;
+    const pam::K3Groups none{};
+    int occ = 0, cus = 0;
+    if (launch_k3(p->precision, p->n_sub, k3_tiles(p), a, none, 0, Target{nullptr, &occ}, p->coherence) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || occ < 1 ||
+        cus < 1) {
+      free_plan(p);
+      return PAM_ERR_DEVICE;
+    }
+    p->k3_slots = occ * cus;
+  }
   *out = p;
   return PAM_OK;
 }
@@ -703,126 +794,243 @@ namespace {
 
 // method 0: angular spectrum (K1, K2, K3 fields, K4); method 1: frequency-domain
 // delay-and-sum (K1, K3 TEA fields, K4; no lateral transform)
-pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
+// Workspace of a grouped call: the groups' layouts back to back (each 256-byte aligned).
+// cap[g]: group g's bins-per-workgroup cap, one cap over the whole call where the fields
+// stage is one grouped launch (factored kernels, more than one group with frames), else
+// each group's own.
+pam_status_t grouped_layout(const pam_plan_s* p, const pam_group_t* groups, int n_groups,
+                            std::vector<pam_workspace_layout_t>& W, std::vector<size_t>& base, size_t* total,
+                            int* cap) {
+  if (n_groups < 1 || n_groups > pam::kMaxGroups || !groups) return PAM_ERR_INVALID_ARG;
+  int64_t F_total = 0;
+  int64_t F[pam::kMaxGroups];
+  int n_sel[pam::kMaxGroups];
+  int live = 0;
+  for (int g = 0; g < n_groups; ++g) {
+    if (groups[g].n_frames < 0) return PAM_ERR_INVALID_ARG;
+    const Level* lv = level_for(p, groups[g].n_t);
+    if (!lv) return PAM_ERR_INVALID_ARG;
+    F[g] = groups[g].n_frames;
+    n_sel[g] = lv->n_sel;
+    F_total += groups[g].n_frames;
+    live += groups[g].n_frames > 0;
+  }
+  if (F_total > 65535) return PAM_ERR_UNSUPPORTED;
+  const int shared = p->ff && live > 1 ? k3_bin_cap(p, F, n_sel, n_groups) : 0;
+  for (int g = 0; g < n_groups; ++g) cap[g] = shared > 0 ? shared : k3_bin_cap(p, &F[g], &n_sel[g], 1);
+  W.resize(n_groups);
+  base.resize(n_groups);
+  size_t o = 0;
+  for (int g = 0; g < n_groups; ++g) {
+    const pam_status_t st = layout(p, groups[g].n_frames, groups[g].n_t, &W[g], cap[g]);
+    if (st != PAM_OK) return st;
+    base[g] = o;
+    o = align256(o + W[g].total);
+  }
+  *total = std::max<size_t>(o, 256);
+  return PAM_OK;
+}
+
+// One call over groups of frames, each group one record length, frames packed group after
+// group in rf and in the outputs.  K1, K2 and K4 run per group; K3 runs as one grouped
+// work list on the factored kernels (else per group).  events: stage marks (one group only).
+pam_status_t run_groups(pam_plan_t p, const float* rf, const pam_group_t* groups, int n_groups, float* image,
                         float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream,
-                        void* const* events, int method = 0) {
-  if (!p || n_frames < 0) return PAM_ERR_INVALID_ARG;
-  if (n_frames > 65535) return PAM_ERR_UNSUPPORTED;
-  pam_workspace_layout_t W;
-  pam_status_t st = layout(p, n_frames, n_t, &W);
+                        void* const* events, int method) {
+  if (!p) return PAM_ERR_INVALID_ARG;
+  std::vector<pam_workspace_layout_t> W;
+  std::vector<size_t> wbase;
+  size_t total = 0;
+  int cap[pam::kMaxGroups];
+  pam_status_t st = grouped_layout(p, groups, n_groups, W, wbase, &total, cap);
   if (st != PAM_OK) return st;
-  if (n_frames == 0) return PAM_OK;
+  if (events && n_groups != 1) return PAM_ERR_INVALID_ARG;
+  int64_t F_total = 0;
+  for (int g = 0; g < n_groups; ++g) F_total += groups[g].n_frames;
+  if (F_total == 0) return PAM_OK;
   if (!rf || !image) return PAM_ERR_INVALID_ARG;
-  if (!workspace || ws_bytes < W.total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return PAM_ERR_WORKSPACE;
+  if (!workspace || ws_bytes < total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return PAM_ERR_WORKSPACE;
   if (rho_pairs && p->n_sub == 1) return PAM_ERR_INVALID_ARG;
-  const Level* lv = level_for(p, n_t);
   DeviceGuard guard(p->device);
   if (!guard.ok) return PAM_ERR_DEVICE;
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-  char* ws = static_cast<char*>(workspace);
-  float2* spectra = reinterpret_cast<float2*>(ws + W.spectra);
-  float2* coeffs = reinterpret_cast<float2*>(ws + W.coeffs);
-  float* scales = reinterpret_cast<float*>(ws + W.scales);
-  float* accum = reinterpret_cast<float*>(ws + W.accum);
-  float* energy = reinterpret_cast<float*>(ws + W.energy);
-  float* weight = reinterpret_cast<float*>(ws + W.weight);
-  float* blockmax = reinterpret_cast<float*>(ws + W.blockmax);
-  const int F = (int)n_frames;
   auto mark = [&](int i) -> bool {
     return !events || hipEventRecord(static_cast<hipEvent_t>(events[i]), stream) == hipSuccess;
   };
   if (!mark(0)) return PAM_ERR_DEVICE;
+  const int pix = p->n_z * p->N;
+  const int n_pairs = p->n_sub == 3 ? 3 : (p->n_sub == 2 ? 1 : 0);
+
+  // per group: its record length level, frames, workspace and output pointers
+  struct G {
+    const Level* lv;
+    int F, n_t;
+    const float* rf;
+    float *image, *nncc, *rho;
+    float2 *spectra, *coeffs;
+    float *scales, *accum, *energy, *weight, *blockmax;
+    LaunchShape s;
+  };
+  std::vector<G> gs(n_groups);
+  {
+    size_t rf_off = 0, out_off = 0;
+    for (int g = 0; g < n_groups; ++g) {
+      G& q = gs[g];
+      q.lv = level_for(p, groups[g].n_t);
+      q.F = (int)groups[g].n_frames;
+      q.n_t = groups[g].n_t;
+      q.rf = rf + rf_off;
+      q.image = image + out_off * pix;
+      q.nncc = nncc ? nncc + out_off * pix : nullptr;
+      q.rho = rho_pairs ? rho_pairs + out_off * n_pairs * pix : nullptr;
+      char* ws = static_cast<char*>(workspace) + wbase[g];
+      q.spectra = reinterpret_cast<float2*>(ws + W[g].spectra);
+      q.coeffs = reinterpret_cast<float2*>(ws + W[g].coeffs);
+      q.scales = reinterpret_cast<float*>(ws + W[g].scales);
+      q.accum = reinterpret_cast<float*>(ws + W[g].accum);
+      q.energy = reinterpret_cast<float*>(ws + W[g].energy);
+      q.weight = reinterpret_cast<float*>(ws + W[g].weight);
+      q.blockmax = reinterpret_cast<float*>(ws + W[g].blockmax);
+      q.s = k3_shape(p, q.lv->n_sel, cap[g]);
+      rf_off += (size_t)q.F * p->L * q.n_t;
+      out_off += (size_t)q.F;
+    }
+  }
 
   // K1: time FFT, one workgroup per (channel, frame)
-  {
-    pam::K1Args a{rf, spectra, p->d_tw, lv->d_ksel, p->L, n_t, ilog2(n_t / 2), lv->stride, lv->n_sel};
-    const size_t lds = (size_t)(n_t / 2) * sizeof(float2);
-    const int M = n_t / 2;
-    const unsigned blocks = (unsigned)(p->L * F);
+  for (const G& q : gs) {
+    if (q.F == 0) continue;
+    pam::K1Args a{q.rf, q.spectra, p->d_tw, q.lv->d_ksel, p->L, q.n_t, ilog2(q.n_t / 2), q.lv->stride, q.lv->n_sel};
+    const size_t lds = (size_t)(q.n_t / 2) * sizeof(float2);
+    const int M = q.n_t / 2;
+    const unsigned blocks = (unsigned)(p->L * q.F);
     if (M <= 2048)
       hipLaunchKernelGGL(pam::k1_time_fft<8>, dim3(blocks), dim3(256), lds, stream, a);
     else if (M == 4096)
       hipLaunchKernelGGL(pam::k1_time_fft<16>, dim3(blocks), dim3(256), lds, stream, a);
     else
       hipLaunchKernelGGL(pam::k1_time_fft<32>, dim3(blocks), dim3(256), lds, stream, a);
-    if (hipGetLastError() != hipSuccess || !mark(1)) return PAM_ERR_DEVICE;
+    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
   }
-  // K2: lateral DFT + fold, one workgroup per (bin, frame)
+  if (!mark(1)) return PAM_ERR_DEVICE;
+  // K2: apodization + lateral transform, per (frame, bin)
   if (method == 0) {
-    const long long items = (long long)F * lv->n_sel;
-    if (items > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
-    pam::K2Args a{spectra, coeffs, scales, p->d_twx, p->d_masks, p->L, p->N, p->n_sub, lv->n_sel,
-                  p->col0, p->col_step, p->ff ? pam::kFfN1 : 0, is_fp16(p->precision) ? 1 : 0, (int32_t)items};
-    if (p->ff) {
-      // factored order: the lateral FFT, one wave per (frame, bin)
-      const dim3 grid((unsigned)((items + 3) / 4));
-      switch (p->N * 4 + p->n_sub) {
-        case 128 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 8>), grid, dim3(256), 0, stream, a); break;
-        case 128 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 8>), grid, dim3(256), 0, stream, a); break;
-        case 128 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 8>), grid, dim3(256), 0, stream, a); break;
-        case 256 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 16>), grid, dim3(256), 0, stream, a); break;
-        case 256 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 16>), grid, dim3(256), 0, stream, a); break;
-        case 256 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 16>), grid, dim3(256), 0, stream, a); break;
-        case 512 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 32>), grid, dim3(256), 0, stream, a); break;
-        case 512 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 32>), grid, dim3(256), 0, stream, a); break;
-        case 512 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 32>), grid, dim3(256), 0, stream, a); break;
-        default: return PAM_ERR_UNSUPPORTED;
+    for (const G& q : gs) {
+      if (q.F == 0) continue;
+      const long long items = (long long)q.F * q.lv->n_sel;
+      if (items > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
+      pam::K2Args a{q.spectra, q.coeffs, q.scales, p->d_twx, p->d_masks, p->L, p->N, p->n_sub, q.lv->n_sel,
+                    p->col0, p->col_step, p->ff ? pam::kFfN1 : 0, is_fp16(p->precision) ? 1 : 0, (int32_t)items};
+      if (p->ff) {
+        // factored order: the lateral FFT, one wave per (frame, bin)
+        const dim3 grid((unsigned)((items + 3) / 4));
+        switch (p->N * 4 + p->n_sub) {
+          case 128 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 8>), grid, dim3(256), 0, stream, a); break;
+          case 128 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 8>), grid, dim3(256), 0, stream, a); break;
+          case 128 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 8>), grid, dim3(256), 0, stream, a); break;
+          case 256 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 16>), grid, dim3(256), 0, stream, a); break;
+          case 256 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 16>), grid, dim3(256), 0, stream, a); break;
+          case 256 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 16>), grid, dim3(256), 0, stream, a); break;
+          case 512 * 4 + 1: hipLaunchKernelGGL((pam::k2_fft<1, 32>), grid, dim3(256), 0, stream, a); break;
+          case 512 * 4 + 2: hipLaunchKernelGGL((pam::k2_fft<2, 32>), grid, dim3(256), 0, stream, a); break;
+          case 512 * 4 + 3: hipLaunchKernelGGL((pam::k2_fft<3, 32>), grid, dim3(256), 0, stream, a); break;
+          default: return PAM_ERR_UNSUPPORTED;
+        }
+      } else {
+        const size_t lds = (size_t)(p->N + 3 * p->L + 2 * p->n_sub * p->N) * sizeof(float2);
+        if (p->n_sub == 3)
+          hipLaunchKernelGGL(pam::k2_lateral<3>, dim3(q.lv->n_sel, q.F), dim3(256), lds, stream, a);
+        else if (p->n_sub == 2)
+          hipLaunchKernelGGL(pam::k2_lateral<2>, dim3(q.lv->n_sel, q.F), dim3(256), lds, stream, a);
+        else
+          hipLaunchKernelGGL(pam::k2_lateral<1>, dim3(q.lv->n_sel, q.F), dim3(256), lds, stream, a);
       }
-    } else {
-      const size_t lds = (size_t)(p->N + 3 * p->L + 2 * p->n_sub * p->N) * sizeof(float2);
-      if (p->n_sub == 3)
-        hipLaunchKernelGGL(pam::k2_lateral<3>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
-      else if (p->n_sub == 2)
-        hipLaunchKernelGGL(pam::k2_lateral<2>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
-      else
-        hipLaunchKernelGGL(pam::k2_lateral<1>, dim3(lv->n_sel, F), dim3(256), lds, stream, a);
+      if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
     }
-    if (hipGetLastError() != hipSuccess || !mark(2)) return PAM_ERR_DEVICE;
-  } else if (!mark(2)) {
-    return PAM_ERR_DEVICE;
   }
+  if (!mark(2)) return PAM_ERR_DEVICE;
   // K3 (frequency-domain delay-and-sum): per-pixel fields and cross-spectra
   if (method == 1) {
-    const LaunchShape s = k3_shape(p, F, lv->n_sel);
-    const int npix = p->n_z * p->N;
-    pam::TeaArgs a{spectra, lv->d_ksel, p->d_subs, p->d_z, accum, p->x_first, p->dx, p->xl_first, p->pitch,
-                   p->fs / ((double)n_t * p->c), p->L, p->N, p->n_z, lv->n_sel, F, s.n_split, s.bins_per_split,
-                   (npix + pam::TEA_THREADS - 1) / pam::TEA_THREADS};
-    const long long blocks = (long long)F * a.n_ptile * s.n_split;
-    if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
-    const size_t lds = (size_t)pam::TEA_BC * p->L * sizeof(float2);
-    if (p->n_sub == 3)
-      hipLaunchKernelGGL(pam::k3_tea<3>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
-    else if (p->n_sub == 2)
-      hipLaunchKernelGGL(pam::k3_tea<2>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
-    else
-      hipLaunchKernelGGL(pam::k3_tea<1>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
-    if (hipGetLastError() != hipSuccess || !mark(3)) return PAM_ERR_DEVICE;
+    for (const G& q : gs) {
+      if (q.F == 0) continue;
+      pam::TeaArgs a{q.spectra, q.lv->d_ksel, p->d_subs, p->d_z, q.accum, p->x_first, p->dx, p->xl_first, p->pitch,
+                     p->fs / ((double)q.n_t * p->c), p->L, p->N, p->n_z, q.lv->n_sel, q.F, q.s.n_split,
+                     q.s.bins_per_split, (pix + pam::TEA_THREADS - 1) / pam::TEA_THREADS};
+      const long long blocks = (long long)q.F * a.n_ptile * q.s.n_split;
+      if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
+      const size_t lds = (size_t)pam::TEA_BC * p->L * sizeof(float2);
+      if (p->n_sub == 3)
+        hipLaunchKernelGGL(pam::k3_tea<3>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
+      else if (p->n_sub == 2)
+        hipLaunchKernelGGL(pam::k3_tea<2>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
+      else
+        hipLaunchKernelGGL(pam::k3_tea<1>, dim3((unsigned)blocks), dim3(pam::TEA_THREADS), lds, stream, a);
+      if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
+    }
   }
   // K3: fused propagate / inverse lateral transform / cross-spectra
   if (method == 0) {
-    const LaunchShape s = k3_shape(p, F, lv->n_sel);
-    pam::K3Args a{coeffs, scales, lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, accum,
-                  p->N, p->n_z, lv->n_sel, F, s.n_dt, s.n_xg, s.n_split, s.bins_per_split, p->zero_evanescent,
-                  lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw, lv->d_ev, p->d_ff_tw2,
-                  p->d_ff_tw_vec, p->d_ff_tw2_vec};
-    const long long blocks = (long long)F * s.n_dt * s.n_xg * s.n_split;
-    if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
-    if (launch_k3(p->precision, p->n_sub, s, a, (int)blocks, stream, p->coherence) != hipSuccess || !mark(3))
-      return PAM_ERR_DEVICE;
+    auto args_for = [&](const G& q) {
+      return pam::K3Args{q.coeffs, q.scales, q.lv->d_kz, p->d_z, p->d_basis, p->d_bhi, p->d_blo, q.accum,
+                         p->N, p->n_z, q.lv->n_sel, q.F, q.s.n_dt, q.s.n_xg, q.s.n_split, q.s.bins_per_split,
+                         p->zero_evanescent, q.lv->d_kzff, p->d_ff_w32, p->d_ff_w16, p->d_ff_tw, q.lv->d_ev,
+                         p->d_ff_tw2, p->d_ff_tw_vec, p->d_ff_tw2_vec};
+    };
+    int live = 0;
+    for (const G& q : gs) live += q.F > 0;
+    if (p->ff && live > 1) {
+      // one launch over every group: a grouped work list on the factored kernels
+      pam::K3Groups grp{};
+      long long blocks = 0;
+      const G* first = nullptr;
+      for (const G& q : gs) {
+        if (q.F == 0) continue;
+        if (!first) first = &q;
+        pam::K3Group& e = grp.g[grp.n++];
+        e = pam::K3Group{q.coeffs, q.scales, q.lv->d_kzff, q.lv->d_ev, q.accum, (int32_t)blocks, q.F, q.lv->n_sel,
+                         q.s.n_split, q.s.bins_per_split};
+        blocks += (long long)q.F * q.s.n_dt * q.s.n_xg * q.s.n_split;
+      }
+      if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
+      if (launch_k3(p->precision, p->n_sub, first->s, args_for(*first), grp, (int)blocks, Target{stream, nullptr}, p->coherence) !=
+          hipSuccess)
+        return PAM_ERR_DEVICE;
+    } else {
+      const pam::K3Groups none{};
+      for (const G& q : gs) {
+        if (q.F == 0) continue;
+        const long long blocks = (long long)q.F * q.s.n_dt * q.s.n_xg * q.s.n_split;
+        if (blocks > 0x7fffffffLL) return PAM_ERR_UNSUPPORTED;
+        if (launch_k3(p->precision, p->n_sub, q.s, args_for(q), none, (int)blocks, Target{stream, nullptr}, p->coherence) !=
+            hipSuccess)
+          return PAM_ERR_DEVICE;
+      }
+    }
   }
+  if (!mark(3)) return PAM_ERR_DEVICE;
   // K4: NCC / weight / energy, then NNCC and image
-  {
-    const int pix = p->n_z * p->N;
+  for (int g = 0; g < n_groups; ++g) {
+    const G& q = gs[g];
+    if (q.F == 0) continue;
     const int n_blk = (pix + 255) / 256;
-    pam::K4Args a{accum, energy, weight, blockmax, rho_pairs, image, nncc, pix, F, W.n_split, p->n_sub, n_blk,
-                  W.n_acc, p->eps};
-    hipLaunchKernelGGL(pam::k4_weight, dim3(n_blk, F), dim3(256), 0, stream, a);
+    pam::K4Args a{q.accum, q.energy, q.weight, q.blockmax, q.rho, q.image, q.nncc, pix, q.F, W[g].n_split,
+                  p->n_sub, n_blk, W[g].n_acc, p->eps};
+    hipLaunchKernelGGL(pam::k4_weight, dim3(n_blk, q.F), dim3(256), 0, stream, a);
     if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
-    hipLaunchKernelGGL(pam::k4_image, dim3(n_blk, F), dim3(256), 0, stream, a);
-    if (hipGetLastError() != hipSuccess || !mark(4)) return PAM_ERR_DEVICE;
+    hipLaunchKernelGGL(pam::k4_image, dim3(n_blk, q.F), dim3(256), 0, stream, a);
+    if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
   }
+  if (!mark(4)) return PAM_ERR_DEVICE;
   return PAM_OK;
+}
+
+pam_status_t run_as_tax(pam_plan_t p, const float* rf, int64_t n_frames, int32_t n_t, float* image,
+                        float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream,
+                        void* const* events, int method = 0) {
+  if (!p || n_frames < 0) return PAM_ERR_INVALID_ARG;
+  if (n_frames > 65535) return PAM_ERR_UNSUPPORTED;
+  const pam_group_t one{n_t, n_frames};
+  return run_groups(p, rf, &one, 1, image, nncc, rho_pairs, workspace, ws_bytes, hip_stream, events, method);
 }
 
 }  // namespace
@@ -849,6 +1057,20 @@ pam_status_t pam_fd_tea_tax(pam_plan_t p, const float* rf, int64_t n_frames, int
 }
 
 void pam_destroy(pam_plan_t p) { free_plan(p); }
+
+pam_status_t pam_workspace_size_grouped(pam_plan_t p, const pam_group_t* groups, int32_t n_groups, size_t* bytes) {
+  if (!p || !bytes) return PAM_ERR_INVALID_ARG;
+  std::vector<pam_workspace_layout_t> W;
+  std::vector<size_t> base;
+  int cap[pam::kMaxGroups];
+  return grouped_layout(p, groups, n_groups, W, base, bytes, cap);
+}
+
+pam_status_t pam_as_tax_grouped(pam_plan_t p, const float* rf, const pam_group_t* groups, int32_t n_groups,
+                                float* image, float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes,
+                                void* hip_stream) {
+  return run_groups(p, rf, groups, n_groups, image, nncc, rho_pairs, workspace, ws_bytes, hip_stream, nullptr, 0);
+}
 
 void pam_debug_fail_allocation(int32_t n) { g_fail_alloc.store(n < 0 ? -1 : n); }
 

@@ -44,6 +44,10 @@ class PlanInfoC(C.Structure):
                 ("device", C.c_int32)]
 
 
+class GroupC(C.Structure):
+    _fields_ = [("n_t", C.c_int32), ("n_frames", C.c_int64)]
+
+
 class LayoutC(C.Structure):
     _fields_ = [("spectra", C.c_size_t), ("coeffs", C.c_size_t), ("scales", C.c_size_t),
                 ("accum", C.c_size_t), ("energy", C.c_size_t), ("weight", C.c_size_t),
@@ -87,6 +91,10 @@ def _lib():
         lib.pam_destroy.restype = None
         lib.pam_status_string.argtypes = [C.c_int]
         lib.pam_status_string.restype = C.c_char_p
+        lib.pam_workspace_size_grouped.argtypes = [vp, C.POINTER(GroupC), i32, C.POINTER(sz)]
+        lib.pam_workspace_size_grouped.restype = C.c_int
+        lib.pam_as_tax_grouped.argtypes = [vp, vp, C.POINTER(GroupC), i32, vp, vp, vp, vp, sz, vp]
+        lib.pam_as_tax_grouped.restype = C.c_int
         lib.pam_debug_fail_allocation.argtypes = [i32]
         lib.pam_debug_fail_allocation.restype = None
         lib.pam_debug_live_allocations.argtypes = []
@@ -164,6 +172,56 @@ def pam_plan(geom, device: int = 0, precision: str = "fp32") -> Plan:
     _check(_lib().pam_plan_get_info(h, C.byref(info)), "pam_plan_get_info")
     del keep
     return Plan(h.value, geom, precision, info)
+
+
+def _groups(groups):
+    """(n_t, n_frames) pairs -> a pam_group_t array."""
+    arr = (GroupC * len(groups))()
+    for k, (n_t, F) in enumerate(groups):
+        arr[k].n_t, arr[k].n_frames = int(n_t), int(F)
+    return arr
+
+
+def pam_workspace_size_grouped(plan: Plan, groups) -> int:
+    n = C.c_size_t(0)
+    _check(_lib().pam_workspace_size_grouped(C.c_void_p(plan.handle), _groups(groups), len(groups), C.byref(n)),
+           "pam_workspace_size_grouped")
+    return n.value
+
+
+def alloc_workspace_grouped(plan: Plan, groups, device="cuda"):
+    import torch
+    return torch.empty(pam_workspace_size_grouped(plan, groups), dtype=torch.uint8, device=device)
+
+
+def pam_as_tax_grouped(plan: Plan, rf, groups, image, nncc=None, rho_pairs=None, workspace=None, stream=None):
+    """Frames of several record lengths in one call: groups = [(n_t, n_frames), ...], rf a
+    contiguous float32 device tensor holding the groups back to back ([n_frames][L][n_t] each),
+    image / nncc [sum n_frames][n_z][n_x] (rho_pairs [..][n_pairs][n_z][n_x]) in that order."""
+    import torch
+    info = plan.info
+    F = sum(int(f) for _, f in groups)
+    want_rf = sum(int(f) * info.n_elements * int(n) for n, f in groups)
+
+    def bad(msg):
+        raise PamError(-1, f"pam_as_tax_grouped: {msg}")
+
+    for name, t, count in (("rf", rf, want_rf), ("image", image, F * info.n_z * info.n_x),
+                           ("nncc", nncc, F * info.n_z * info.n_x),
+                           ("rho_pairs", rho_pairs, F * info.n_pairs * info.n_z * info.n_x)):
+        if t is None:
+            if name in ("rf", "image"):
+                bad(f"{name} is required")
+            continue
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            bad(f"{name} must be a contiguous float32 device tensor")
+        if t.numel() != count:
+            bad(f"{name} holds {t.numel()} values, expected {count}")
+    stream = stream or torch.cuda.current_stream()
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(_lib().pam_as_tax_grouped(C.c_void_p(plan.handle), _ptr(rf), _groups(groups), len(groups), _ptr(image),
+                                     _ptr(nncc), _ptr(rho_pairs), _ptr(workspace), ws_bytes,
+                                     C.c_void_p(stream.cuda_stream)), "pam_as_tax_grouped")
 
 
 def debug_fail_allocation(n: int) -> None:
@@ -271,7 +329,7 @@ def pam_fd_tea_tax(plan: Plan, rf, image, nncc=None, rho_pairs=None, workspace=N
     _check(st, "pam_fd_tea_tax")
 
 
-NOALLOC_SCRATCH_BYTES = 64 << 20
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 def pam_as_tax_noalloc(plan: Plan, rf, image, nncc=None, rho_pairs=None, stream=None,

@@ -472,3 +472,41 @@ def test_injected_allocation_failure_leaks_nothing(pam, torch_cuda):
     finally:
         pam.pam_destroy(plan)
     assert pam.debug_live_allocations() == base
+
+
+@pytest.mark.parametrize("geom_name", ["cfg1", "cfg2", "cfg3"])
+def test_workspace_never_shrinks(pam, torch_cuda, geom_name):
+    """The bin split changes with the frame count, but the workspace size never shrinks
+    as frames or record length grow, and the accum region always holds the n_split F
+    planes the chosen split writes; a workspace sized for 64 frames then serves a call of
+    23 frames with the same results as a workspace sized for 23."""
+    g = getattr(synth, f"{geom_name}_geometry")()
+    plan = pam.pam_plan(g, 0, "fp32")
+    try:
+        pix = g.n_z * g.n_x
+        lengths = [g.n_samples >> j for j in range(3)][::-1]
+        prev_t = 0
+        for n_t in lengths:
+            prev = 0
+            for F in list(range(0, 70)) + [96, 128, 200]:
+                lay = pam.pam_workspace_layout(plan, F, n_t)
+                assert lay.total >= prev, (n_t, F)
+                prev = lay.total
+                room = (lay.energy - lay.accum) // 4
+                assert room >= lay.n_split * F * lay.n_acc * pix, (n_t, F, lay.n_split)
+            assert pam.pam_workspace_size(plan, 64, n_t) >= prev_t
+            prev_t = pam.pam_workspace_size(plan, 64, n_t)
+        F = 23
+        rf = np.stack([synth.cfg1_frame(s) for s in range(F)]) if geom_name == "cfg1" else None
+        if rf is not None:
+            x = torch_cuda.from_numpy(rf).cuda()
+            outs = []
+            for n_ws in (F, 64):
+                ws = pam.alloc_workspace(plan, n_ws, g.n_samples)
+                img = torch_cuda.empty((F, g.n_z, g.n_x), device="cuda")
+                pam.pam_as_tax(plan, x, img, None, None, ws)
+                torch_cuda.cuda.synchronize()
+                outs.append(img.cpu().numpy())
+            np.testing.assert_array_equal(outs[0], outs[1])
+    finally:
+        pam.pam_destroy(plan)

@@ -100,3 +100,49 @@ def test_mixed_record_lengths_on_one_plan(env):
             for k in range(len(idx)):
                 e = float(np.linalg.norm(img[k] - img32[k]) / np.linalg.norm(img32[k]))
                 assert e <= 1e-3 and float(np.abs(rho[k] - rho32[k]).max()) <= 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_grouped_call_mixes_record_lengths(env, precision):
+    """The 64 mixed-length frames of the cfg1 array in ONE call (groups of 2048 / 4096 / 8192
+    samples back to back, with an empty group in between): every frame equals the per-length
+    call on the same frames up to summation order, and the first frame of each length
+    matches the FP64 oracle at the form's tolerance.  In FP32 the fields stage is one grouped
+    work-list launch over all lengths."""
+    torch, pam = env
+    g = synth.cfg3_geometry()
+    frames = [synth.cfg3_frame(s) for s in range(64)]
+    lengths = sorted({fr.shape[-1] for fr in frames})
+    order = {n: [i for i, fr in enumerate(frames) if fr.shape[-1] == n] for n in lengths}
+    groups = [(lengths[0], len(order[lengths[0]])), (lengths[1], 0)] + [(n, len(order[n])) for n in lengths[1:]]
+    packed = np.concatenate([np.stack([frames[i] for i in order[n]]).ravel() for n in lengths]).astype(np.float32)
+    plan = pam.pam_plan(g, 0, precision)
+    try:
+        F = sum(f for _, f in groups)
+        rf = torch.from_numpy(packed).cuda()
+        img = torch.empty((F, g.n_z, g.n_x), device="cuda")
+        rho = torch.empty_like(img)
+        ws = pam.alloc_workspace_grouped(plan, groups)
+        pam.pam_as_tax_grouped(plan, rf, groups, img, rho, None, ws)
+        torch.cuda.synchronize()
+        img, rho = img.cpu().numpy().astype(np.float64), rho.cpu().numpy().astype(np.float64)
+        with pytest.raises(pam.PamError):
+            pam.pam_workspace_size_grouped(plan, [(1000, 3)])                 # not a record length of the plan
+        with pytest.raises(pam.PamError):
+            pam.pam_workspace_size_grouped(plan, [(lengths[0], 1)] * 9)       # more than 8 groups
+    finally:
+        pam.pam_destroy(plan)
+    tol_i, tol_r = (1e-5, 1e-4) if precision == "fp32" else (1e-3, 1e-3)
+    k = 0
+    for n in lengths:
+        idx = order[n]
+        alone_i, alone_r = gpu_run(env, g, np.stack([frames[i] for i in idx]), precision)
+        for j in range(len(idx)):
+            e = float(np.linalg.norm(img[k + j] - alone_i[j]) / np.linalg.norm(alone_i[j]))
+            assert e <= 1e-5 and float(np.abs(rho[k + j] - alone_r[j]).max()) <= 1e-4, (n, j, e)
+        ref = O.as_tax(frames[idx[0]], g.replace(n_samples=n))
+        e_i, e_r = errors(img[k], rho[k], ref)
+        print(f"{precision} n_t={n} ({len(idx)} frames): grouped vs oracle relL2(I)={e_i:.3e} "
+              f"max|d rho_n|={e_r:.3e}", flush=True)
+        assert e_i <= tol_i and e_r <= tol_r
+        k += len(idx)
