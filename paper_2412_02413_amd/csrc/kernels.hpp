@@ -79,6 +79,7 @@ struct K1Args {
   const float2* tw;       // e^{-2 pi i m / n_tp}, m < n_tp/2 (plan grid)
   const int32_t* ksel;    // bin k on the call's grid, [n_sel]
   int32_t L, n_t, log2m, tw_stride, n_sel;
+  int32_t F;              // frames: the kernel walks the L F channels
 };
 
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // times -i
@@ -116,32 +117,42 @@ __device__ __forceinline__ void dft8(float2* v) {
   v[7] = csub(e3, o3);
 }
 
-// One Stockham pass of radix R over M points; EPT = elements per thread, so each
-// thread runs EPT / R butterflies j = tid + 256 w.  Operands come from global memory
-// on the first pass (Ns = 1) and from LDS afterwards.
-template <int R, int EPT>
-__device__ __forceinline__ void stockham_pass(const float2* src, float2* z, int M, int Ns, int tid) {
-  constexpr int PER = EPT / R;
-  const int nbf = M / R;
-  float2 v[PER][R];
+// LDS slot of point i of the K1 transform: one pad slot after every 8 points, so that the
+// radix-8 pass writes (lane stride 8 points at NS = 1, runs of 8 at NS = 8) spread over
+// the LDS banks instead of landing 8 to 16 lanes on one bank.
+__device__ __forceinline__ int k1_slot(int i) { return i + (i >> 3); }
+template <int M>
+__host__ __device__ constexpr int k1_lds_points() { return M + M / 8; }
+
+// One Stockham pass of radix R over M = 2^LOGM points, NS of them already transformed.
+// EPT = elements per thread, so each thread runs EPT / R butterflies j = tid + 256 w.
+// The first pass (NS = 1) takes its operands from registers v (loaded from global memory
+// by k1_load), later passes from LDS.  Sizes and strides are compile-time constants, so
+// the index arithmetic folds away and the pass needs few registers.
+template <int LOGM, int R, int NS, int EPT>
+__device__ __forceinline__ void k1_pass(float2 (&v)[EPT / R][R], float2* z, int tid) {
+  constexpr int M = 1 << LOGM, NBF = M / R, PER = EPT / R;
+  constexpr bool ALL = PER * 256 == NBF;   // every butterfly slot j = tid + 256 w is a butterfly
+  if constexpr (NS > 1) {
 #pragma unroll
-  for (int w = 0; w < PER; ++w) {
-    const int j = tid + 256 * w;
-    if (j < nbf) {
+    for (int w = 0; w < PER; ++w) {
+      const int j = tid + 256 * w;
+      if (ALL || j < NBF) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[w][r] = Ns == 1 ? src[j + r * nbf] : z[j + r * nbf];
+        for (int r = 0; r < R; ++r) v[w][r] = z[k1_slot(j + r * NBF)];
+      }
     }
+    __syncthreads();   // every read of this pass is done before any write
   }
-  if (Ns > 1) __syncthreads();   // every read of this pass is done before any write
 #pragma unroll
   for (int w = 0; w < PER; ++w) {
     const int j = tid + 256 * w;
-    if (j < nbf) {
-      const int k = j & (Ns - 1);
-      if (Ns > 1) {
-        // w1 = e^{-2 pi i k / (Ns R)} from the hardware sine/cosine (argument in cycles,
+    if (ALL || j < NBF) {
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
+        // w1 = e^{-2 pi i k / (NS R)} from the hardware sine/cosine (argument in cycles,
         // an exact dyadic fraction), its higher powers by products
-        const float c = (float)k / (float)(Ns * R);
+        const float c = (float)k * (1.0f / (float)(NS * R));
         const float2 w1 = make_float2(__builtin_amdgcn_cosf(c), -__builtin_amdgcn_sinf(c));
         float2 wr = w1;
 #pragma unroll
@@ -155,43 +166,114 @@ __device__ __forceinline__ void stockham_pass(const float2* src, float2* z, int 
       else dft2(v[w]);
       const int idx = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) z[idx + r * Ns] = v[w][r];
+      for (int r = 0; r < R; ++r) z[k1_slot(idx + r * NS)] = v[w][r];
     }
   }
   __syncthreads();
 }
 
-// EPT = elements per thread = max(8, M / 256).  One-dimensional grid of L F
-// workgroups; consecutive workgroups go round-robin to the 8 XCDs, so the index is
-// remapped to give each XCD runs of consecutive channels of a frame: their bin writes
-// (stride L) then fill the same cache lines of one L2.
-template <int EPT>
-__global__ __launch_bounds__(256) void k1_time_fft(K1Args a) {
-  extern __shared__ float2 z[];  // [M]
+// Radix of the K1 pass at NS: 8 while at least 8 points remain, then 4 or 2.
+template <int M, int NS>
+__host__ __device__ constexpr int k1_radix() { return M / NS >= 8 ? 8 : (M / NS == 4 ? 4 : 2); }
+
+// The passes after the first: NS = R0 onwards.
+template <int LOGM, int NS, int EPT>
+__device__ __forceinline__ void k1_passes(float2* z, int tid) {
+  constexpr int M = 1 << LOGM;
+  if constexpr (NS < M) {
+    constexpr int R = k1_radix<M, NS>();
+    float2 v[EPT / R][R];
+    k1_pass<LOGM, R, NS, EPT>(v, z, tid);
+    k1_passes<LOGM, NS * R, EPT>(z, tid);
+  }
+}
+
+// The first pass's operands of one channel: butterfly j = tid + 256 w reads points
+// j + r M / R0 (coalesced: consecutive threads take consecutive j).
+template <int LOGM, int PER, int R>
+__device__ __forceinline__ void k1_load(float2 (&v)[PER][R], const float2* src, int tid) {
+  constexpr int M = 1 << LOGM, NBF = M / R;
+  constexpr bool ALL = PER * 256 == NBF;
+  static_assert(R == k1_radix<M, 1>(), "first-pass radix");
+#pragma unroll
+  for (int w = 0; w < PER; ++w) {
+    const int j = tid + 256 * w;
+    if (ALL || j < NBF) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[w][r] = src[j + r * NBF];
+    }
+  }
+}
+
+// M = 2^LOGM = n_t / 2 complex points; EPT = elements per thread = max(8, M / 256).  A
+// workgroup holds CH channels of one frame (elements l0 .. l0 + CH - 1), 256 threads and
+// an LDS block per channel.  With CH = 2 a thread of the bin step writes one bin of both
+// channels as one 16-byte store: half the store requests of one channel per workgroup,
+// whose 8-byte stores each hit their own cache line (the bins of a channel lie L apart).
+// Up to M = 2048 a thread holds 8 points and the kernel fits eight waves per SIMD.  The
+// kernel is persistent: workgroup bid takes channel groups item = bid, bid + G, ... of the
+// L F / CH; once the first pass has put a group into LDS, the next group's samples are
+// loaded into the registers it freed, so those HBM reads overlap the later LDS passes and
+// the bin writes of this one.  Consecutive workgroups go round-robin to the 8 XCDs, so the
+// index is remapped to give each XCD runs of consecutive channel groups of a frame: their
+// bin writes then fill the same cache lines of one L2.
+template <int LOGM, int CH = 1, int EPT = (LOGM <= 11 ? 8 : (1 << LOGM) / 256)>
+__global__ __launch_bounds__(256 * CH, EPT == 8 ? 8 : 2) void k1_time_fft(K1Args a) {
+  extern __shared__ float2 k1_lds[];  // CH x [k1_lds_points<M>()], point i at k1_slot(i)
+  constexpr int M = 1 << LOGM, R0 = k1_radix<M, 1>();
+  static_assert(CH == 1 || (CH == 2 && EPT == 8), "two channels per workgroup up to 4096 samples");
   const int G = gridDim.x;
   int bid = blockIdx.x;
   if ((G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
-  const int l = bid % a.L, f = bid / a.L;
-  const int M = a.n_t >> 1;
-  const int tid = threadIdx.x;
-  const float2* src = reinterpret_cast<const float2*>(a.rf + ((size_t)f * a.L + l) * a.n_t);
-  for (int Ns = 1; Ns < M;) {
-    const int R = (M / Ns >= 8) ? 8 : ((M / Ns == 4) ? 4 : 2);
-    if (R == 8) stockham_pass<8, EPT>(src, z, M, Ns, tid);
-    else if (R == 4) stockham_pass<4, EPT>(src, z, M, Ns, tid);
-    else stockham_pass<2, EPT>(src, z, M, Ns, tid);
-    Ns *= R;
-  }
-  float2* dst = a.spectra + (size_t)f * a.n_sel * a.L + l;
-  for (int b = tid; b < a.n_sel; b += 256) {
-    const int k = a.ksel[b];               // 0 < k < M
-    const float2 zk = z[k];
-    const float2 zc = make_float2(z[M - k].x, -z[M - k].y);
-    const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-    const float2 d = csub(zk, zc);
-    const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // (zk - zc) / (2i)
-    const float2 w = a.tw[k * a.tw_stride];                   // e^{-2 pi i k / n_t}
-    dst[(size_t)b * a.L] = cadd(e, cmul(w, o));
+  const int groups = a.L / CH;                 // channel groups per frame
+  const int n_items = groups * a.F;
+  const int sub = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  float2* z = k1_lds + sub * k1_lds_points<M>();
+  float2 v[EPT / R0][R0];
+  // channel of this thread's sub-group in group item: frame item / groups, element
+  // (item % groups) CH + sub, i.e. row item CH + sub of [F][L]
+  if (bid < n_items)
+    k1_load<LOGM>(v, reinterpret_cast<const float2*>(a.rf + ((size_t)bid * CH + sub) * a.n_t), tid);
+  for (int item = bid; item < n_items; item += G) {
+    // the thread index, opaque to the compiler once per group: every twiddle and LDS
+    // address derived from it is recomputed in each pass rather than hoisted out of the
+    // loop and held in registers across it
+    int t = tid;
+    asm volatile("" : "+v"(t));
+    k1_pass<LOGM, R0, 1, EPT>(v, z, t);       // consumes v
+    if (item + G < n_items)                   // in flight during the remaining passes
+      k1_load<LOGM>(v, reinterpret_cast<const float2*>(a.rf + ((size_t)(item + G) * CH + sub) * a.n_t), t);
+    k1_passes<LOGM, R0, EPT>(z, t);
+    const int l0 = (item % groups) * CH, f = item / groups;
+    float2* dst = a.spectra + (size_t)f * a.n_sel * a.L + l0;
+    // X[k] = E[k] + e^{-2 pi i k / n_t} O[k], E and O from Z[k] and conj Z[M - k]
+    auto bin = [&](const float2* zz, int k, float2 w) {
+      const float2 zk = zz[k1_slot(k)];
+      const float2 zm = zz[k1_slot(M - k)];
+      const float2 zc = make_float2(zm.x, -zm.y);
+      const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+      const float2 d = csub(zk, zc);
+      const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // (zk - zc) / (2i)
+      return cadd(e, cmul(w, o));
+    };
+    if constexpr (CH == 1) {
+      for (int b = t; b < a.n_sel; b += 256) {
+        const int k = a.ksel[b];               // 0 < k < M
+        dst[(size_t)b * a.L] = bin(z, k, a.tw[k * a.tw_stride]);
+      }
+    } else {
+      // thread (b, pair): bin b of channels l0 + 2 pair and l0 + 2 pair + 1 (one pair)
+      constexpr int PAIRS = CH / 2;
+      for (int u = (int)threadIdx.x; u < PAIRS * a.n_sel; u += 256 * CH) {
+        const int b = u / PAIRS, pr = u % PAIRS;
+        const int k = a.ksel[b];
+        const float2 w = a.tw[k * a.tw_stride];   // e^{-2 pi i k / n_t}
+        const float2 x0 = bin(k1_lds + (2 * pr) * k1_lds_points<M>(), k, w);
+        const float2 x1 = bin(k1_lds + (2 * pr + 1) * k1_lds_points<M>(), k, w);
+        *reinterpret_cast<float4*>(dst + (size_t)b * a.L + 2 * pr) = make_float4(x0.x, x0.y, x1.x, x1.y);
+      }
+    }
+    __syncthreads();                         // the next group's first pass overwrites z
   }
 }
 

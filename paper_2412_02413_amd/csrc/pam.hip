@@ -120,6 +120,7 @@ struct pam_plan_s {
   double xl_first = 0, pitch = 0;  // coordinate of element 0 and element pitch
   int32_t* d_subs = nullptr;   // [L] bit i set if sub-aperture i holds element l
   int k3_slots = 512;          // K3 workgroups resident on the device at once
+  int n_cus = 256;             // compute units of the plan's device
   std::vector<void*> allocs;
 };
 
@@ -751,6 +752,7 @@ pam_status_t pam_plan(const pam_geometry_t* g, int device, pam_plan_t* out) {
       return PAM_ERR_DEVICE;
     }
     p->k3_slots = occ * cus;
+    p->n_cus = cus;
   }
   *out = p;
   return PAM_OK;
@@ -900,16 +902,50 @@ pam_status_t run_groups(pam_plan_t p, const float* rf, const pam_group_t* groups
   // K1: time FFT, one workgroup per (channel, frame)
   for (const G& q : gs) {
     if (q.F == 0) continue;
-    pam::K1Args a{q.rf, q.spectra, p->d_tw, q.lv->d_ksel, p->L, q.n_t, ilog2(q.n_t / 2), q.lv->stride, q.lv->n_sel};
-    const size_t lds = (size_t)(q.n_t / 2) * sizeof(float2);
-    const int M = q.n_t / 2;
-    const unsigned blocks = (unsigned)(p->L * q.F);
-    if (M <= 2048)
-      hipLaunchKernelGGL(pam::k1_time_fft<8>, dim3(blocks), dim3(256), lds, stream, a);
-    else if (M == 4096)
-      hipLaunchKernelGGL(pam::k1_time_fft<16>, dim3(blocks), dim3(256), lds, stream, a);
-    else
-      hipLaunchKernelGGL(pam::k1_time_fft<32>, dim3(blocks), dim3(256), lds, stream, a);
+    pam::K1Args a{q.rf, q.spectra, p->d_tw, q.lv->d_ksel, p->L, q.n_t, ilog2(q.n_t / 2), q.lv->stride, q.lv->n_sel,
+                  q.F};
+    // two channels per workgroup where they divide L (up to 4096 samples), else one
+    const int ch = (p->L % 2 == 0 && q.n_t <= 4096) ? 2 : 1;
+    const size_t lds = (size_t)ch * (q.n_t / 2 + q.n_t / 16) * sizeof(float2);   // ch k1_lds_points
+    const long long items = (long long)p->L / ch * q.F;
+    auto k1 = [&](auto kernel) -> bool {
+      // n_t = 16384 takes more than 64 KiB of LDS: the kernel needs the attribute
+      if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return false;
+      // persistent: as many workgroups as the device holds at once (each walks its channels)
+      int occ = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kernel), 256 * ch, lds) !=
+              hipSuccess ||
+          occ < 1)
+        return false;
+      const unsigned blocks = (unsigned)std::min<long long>(items, (long long)occ * p->n_cus);
+      hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256 * ch), lds, stream, a);
+      return true;
+    };
+    bool ok = false;
+    switch (ilog2(q.n_t / 2) * 8 + ch) {   // n_t = 32 .. 16384
+      case 4 * 8 + 1: ok = k1(pam::k1_time_fft<4>); break;
+      case 5 * 8 + 1: ok = k1(pam::k1_time_fft<5>); break;
+      case 6 * 8 + 1: ok = k1(pam::k1_time_fft<6>); break;
+      case 7 * 8 + 1: ok = k1(pam::k1_time_fft<7>); break;
+      case 8 * 8 + 1: ok = k1(pam::k1_time_fft<8>); break;
+      case 9 * 8 + 1: ok = k1(pam::k1_time_fft<9>); break;
+      case 10 * 8 + 1: ok = k1(pam::k1_time_fft<10>); break;
+      case 11 * 8 + 1: ok = k1(pam::k1_time_fft<11>); break;
+      case 12 * 8 + 1: ok = k1(pam::k1_time_fft<12>); break;
+      case 13 * 8 + 1: ok = k1(pam::k1_time_fft<13>); break;
+      case 4 * 8 + 2: ok = k1(pam::k1_time_fft<4, 2>); break;
+      case 5 * 8 + 2: ok = k1(pam::k1_time_fft<5, 2>); break;
+      case 6 * 8 + 2: ok = k1(pam::k1_time_fft<6, 2>); break;
+      case 7 * 8 + 2: ok = k1(pam::k1_time_fft<7, 2>); break;
+      case 8 * 8 + 2: ok = k1(pam::k1_time_fft<8, 2>); break;
+      case 9 * 8 + 2: ok = k1(pam::k1_time_fft<9, 2>); break;
+      case 10 * 8 + 2: ok = k1(pam::k1_time_fft<10, 2>); break;
+      case 11 * 8 + 2: ok = k1(pam::k1_time_fft<11, 2>); break;
+      default: return PAM_ERR_UNSUPPORTED;
+    }
+    if (!ok) return PAM_ERR_DEVICE;
     if (hipGetLastError() != hipSuccess) return PAM_ERR_DEVICE;
   }
   if (!mark(1)) return PAM_ERR_DEVICE;

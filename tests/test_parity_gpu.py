@@ -362,17 +362,19 @@ def test_largest_serving_frame(pam, torch_cuda, precision):
     check_end_to_end(res, ref, tol_i=tol_i, tol_rho=tol_rho)
 
 
-@pytest.mark.parametrize("n_t", [32, 256, 4096, 16384])
-def test_stage_time_fft_record_lengths(pam, torch_cuda, n_t):
+@pytest.mark.parametrize("n_t,L", [(32, 8), (256, 8), (256, 7), (2048, 6), (4096, 8), (4096, 9), (16384, 8)])
+def test_stage_time_fft_record_lengths(pam, torch_cuda, n_t, L):
     """K1 (the time FFT) on every pass structure it runs: 32 samples (radix 8 then 2),
-    256 (8, 8, 2), 4096 (8, 8, 8, 4), 16384 (8, 8, 8, 8, 2 with 32 points per thread)."""
-    g = synth.Geometry(n_elements=8, pitch_m=0.3 * MM, fs_hz=20e6, c_mps=1540.0, n_samples=n_t,
+    256 (8, 8, 2), 2048 (8, 8, 8, 2), 4096 (8, 8, 8, 4), 16384 (8, 8, 8, 8, 2 with 32 points
+    per thread); two channels per workgroup where 2 divides L (up to 4096 samples), one
+    otherwise (L = 7 and 9, and 16384 samples)."""
+    g = synth.Geometry(n_elements=L, pitch_m=0.3 * MM, fs_hz=20e6, c_mps=1540.0, n_samples=n_t,
                        bands_hz=[(0.0, 10e6)], depths_m=np.array([20.0, 20.5]) * MM, n_x=32, lateral="pad")
-    rng = np.random.default_rng(n_t)
-    rf = rng.standard_normal((2, 8, n_t)).astype(np.float32)
+    rng = np.random.default_rng(n_t + L)
+    rf = rng.standard_normal((2, L, n_t)).astype(np.float32)
     res = run(pam, torch_cuda, g, rf)
     lay = res["layout"]
-    F, n_sel, L = 2, lay.n_sel, g.n_elements
+    F, n_sel = 2, lay.n_sel
     assert n_sel == n_t // 2 - 1
     X = ws_view(torch_cuda, res["ws"], lay.spectra, F * n_sel * L, np.complex64).reshape(F, n_sel, L)
     for f in range(F):
