@@ -421,7 +421,7 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a0, K3Groups grp) {
         pim[i] = SCALED ? C[i][v + 8] * inv : C[i][v + 8];
         if constexpr (R == 2) {
           // P_0 +- w P_1: lane half zz = 0 holds P_0(x'), zz = 1 P_1(x'), x' its column
-          const float or_ = __shfl_xor(pr[i], 16), oi = __shfl_xor(pim[i], 16);
+          const float or_ = lane_xor16(pr[i]), oi = lane_xor16(pim[i]);
           const float2 p0 = zz ? make_float2(or_, oi) : make_float2(pr[i], pim[i]);
           const float2 p1 = zz ? make_float2(pr[i], pim[i]) : make_float2(or_, oi);
           const float2 t = cmul(tw2.t[v], p1);
@@ -439,8 +439,8 @@ __global__ __launch_bounds__(512, 1) void k3ff(K3Args a0, K3Groups grp) {
       }
       if constexpr (COH) {
         // partner fields: column x ^ 1 sits in lane ^ 1, depth zz ^ 1 in lane ^ 16
-        const float lr = __shfl_xor(pr[0], 1), li = __shfl_xor(pim[0], 1);
-        const float zr = __shfl_xor(pr[0], 16), zi = __shfl_xor(pim[0], 16);
+        const float lr = lane_xor1(pr[0]), li = lane_xor1(pim[0]);
+        const float zr = lane_xor16(pr[0]), zi = lane_xor16(pim[0]);
         accG[0][v] = fmaf(pr[0], lr, fmaf(pim[0], li, accG[0][v]));
         accG[1][v] = fmaf(pim[0], lr, fmaf(-pr[0], li, accG[1][v]));
         accG[2][v] = fmaf(pr[0], zr, fmaf(pim[0], zi, accG[2][v]));

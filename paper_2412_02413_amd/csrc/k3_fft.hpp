@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
         // P_0 +- w P_1: group parity e = 0 holds P_0(x'), e = 1 P_1(x'), x' = j + 16 x2
 #pragma unroll
         for (int x2 = 0; x2 < 16; ++x2) {
-          const float2 o = make_float2(__shfl_xor(p[i][x2].x, 16), __shfl_xor(p[i][x2].y, 16));
+          const float2 o = make_float2(lane_xor16(p[i][x2].x), lane_xor16(p[i][x2].y));
           const float2 p0 = e ? o : p[i][x2], p1 = e ? p[i][x2] : o;
           const float2 t = cmul(twl[256 + x2 * 16 + j], p1);
           p[i][x2] = e ? f2sub(p0, t) : f2add(p0, t);
@@ -302,8 +302,8 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
       }
       if constexpr (COH) {
         const float pr = p[0][x2].x, pi = p[0][x2].y;
-        const float lr = __shfl_xor(pr, 1), li = __shfl_xor(pi, 1);
-        const float zr = __shfl_xor(pr, 16), zi = __shfl_xor(pi, 16);
+        const float lr = lane_xor1(pr), li = lane_xor1(pi);
+        const float zr = lane_xor16(pr), zi = lane_xor16(pi);
         accG[0][x2] = fmaf(pr, lr, fmaf(pi, li, accG[0][x2]));
         accG[1][x2] = fmaf(pi, lr, fmaf(-pr, li, accG[1][x2]));
         accG[2][x2] = fmaf(pr, zr, fmaf(pi, zi, accG[2][x2]));

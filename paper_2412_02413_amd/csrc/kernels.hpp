@@ -82,6 +82,16 @@ struct K1Args {
   int32_t F;              // frames: the kernel walks the L F channels
 };
 
+// The value lane ^ 1 holds: DPP quad permutation [1, 0, 3, 2], a vector-ALU move.
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+// The value lane ^ 16 holds: ds_swizzle in bit mode (and 0x1F, or 0, xor 0x10 within each
+// 32 lanes), which moves data through the LDS crossbar without touching LDS memory.
+__device__ __forceinline__ float lane_xor16(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+}
+
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // times -i
 
 // in-place forward DFTs of 2, 4 and 8 points (e^{-2 pi i / R})

@@ -329,7 +329,10 @@ def test_resumed_training_follows_the_same_trajectory(env, small_data):
     """A run checkpointed after 4 steps (master weights, Adam moments and step, the batch
     sampler's generator state) and resumed in a fresh network retraces the next 4 losses and
     ends at the same parameters.  The weight gradients sum with atomics, so the agreement
-    is to FP32 rounding, not bit for bit."""
+    is to FP32 rounding, not bit for bit: a parameter may differ by 1e-4 of its tensor's
+    largest magnitude plus 1 % of the most Adam can move it in the 4 resumed steps
+    (lr per step).  Resuming without the moments, the step count or the sampler state moves
+    parameters by O(lr) per step and changes the losses, which both bounds catch."""
     import copy
     torch, nn, S = env
     g, A, R, _, _ = small_data
@@ -351,4 +354,4 @@ def test_resumed_training_follows_the_same_trajectory(env, small_data):
     assert other.step_count == net.step_count == 8
     for k in net.params:
         d = (net.params[k] - other.params[k]).abs().max().item()
-        assert d <= 1e-4 * max(net.params[k].abs().max().item(), 1e-6), k
+        assert d <= 1e-4 * net.params[k].abs().max().item() + 0.01 * 4 * 3e-4, (k, d)
