@@ -92,6 +92,13 @@ __device__ __forceinline__ float lane_xor16(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
 }
 
+// The value lane (16 - i) mod 16 of the lane's row of 16 holds (i = lane index in the row): a DPP row
+// rotation by 15 (lane i takes lane i + 1 mod 16) followed by a DPP row mirror (lane i takes lane 15 - i).
+__device__ __forceinline__ float lane_mirror16(float v) {
+  const int t = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x12F, 0xF, 0xF, false);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(t, 0x140, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // times -i
 
 // in-place forward DFTs of 2, 4 and 8 points (e^{-2 pi i / R})
