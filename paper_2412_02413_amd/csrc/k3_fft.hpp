@@ -267,10 +267,12 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
     const double* kzr = reinterpret_cast<const double*>(st + NSUB * ROWS * kFfRow) + srow * kFfRow;
     // propagator at q = 16 m + j (N = 256) or 32 m + 2 j + e (N = 512) (Eq. 2): phase in FP64 reduced to [-1/2, 1/2] cycle,
     // hardware sin/cos; evanescent values replaced in a branch only lanes holding any take.
-    // At N = 256, kz(q) = kz(N - q) and N - (16 m + j) = 16 (15 - m) + (16 - j): lane j's H[m] for m > 8 is lane
-    // (16 - j)'s H[15 - m] (same depth), and lane 0's is its own H[16 - m].  So a lane computes H[0..8] and takes
-    // the other seven from its partner lane.
-    constexpr int MD = NN == 256 ? 9 : 16;   // values computed directly
+    // kz(q) = kz(N - q).  At N = 256, N - (16 m + j) = 16 (15 - m) + (16 - j): lane j's H[m] for m > 8 is lane
+    // (16 - j)'s H[15 - m] (same depth), and lane 0's is its own H[16 - m].  At N = 128 (q = 8 m + q2, q2 = j % 8,
+    // one depth per 8 lanes) the partner of q2 is 8 - q2 in the same 8 lanes, and q2 = 0 pairs with itself.  So a
+    // lane computes H[0..8] and takes the other seven from its partner lane.
+    constexpr bool SYM = NN == 256 || NN == 128;
+    constexpr int MD = SYM ? 9 : 16;   // values computed directly
     float2 H[16];
 #pragma unroll
     for (int m = 0; m < MD; ++m) {
@@ -283,11 +285,13 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
       for (int m = 0; m < MD; ++m)
         if (kzr[m] < 0.0) H[m] = propagator(z, kzr[m], a.zero_evanescent);
     }
-    if constexpr (NN == 256) {
+    if constexpr (SYM) {
+      const bool self = (HALF ? (j & 7) : j) == 0;
 #pragma unroll
       for (int m = MD; m < 16; ++m) {
-        const float2 o = make_float2(lane_mirror16(H[15 - m].x), lane_mirror16(H[15 - m].y));
-        H[m] = j == 0 ? H[16 - m] : o;
+        const float2 o = HALF ? make_float2(lane_mirror8(H[15 - m].x), lane_mirror8(H[15 - m].y))
+                              : make_float2(lane_mirror16(H[15 - m].x), lane_mirror16(H[15 - m].y));
+        H[m] = self ? H[16 - m] : o;
       }
     }
     float2 p[NSUB][16];

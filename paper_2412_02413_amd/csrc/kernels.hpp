@@ -99,6 +99,14 @@ __device__ __forceinline__ float lane_mirror16(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(t, 0x140, 0xF, 0xF, false));
 }
 
+// The value lane (8 - i) mod 8 of the lane's group of 8 holds (i = lane index in the group), for i = 1..7: the
+// row rotation by 15 (lane i takes lane i + 1 mod 16) followed by a DPP half-row mirror (lane i takes lane 7 - i
+// of its 8).  Lane 0 of each group receives a value from outside its group; callers use it only for i > 0.
+__device__ __forceinline__ float lane_mirror8(float v) {
+  const int t = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x12F, 0xF, 0xF, false);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(t, 0x141, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // times -i
 
 // in-place forward DFTs of 2, 4 and 8 points (e^{-2 pi i / R})
