@@ -235,11 +235,11 @@ __device__ __forceinline__ void k1_load(float2 (&v)[PER][R], const float2* src, 
 // an LDS block per channel.  With CH = 2 a thread of the bin step writes one bin of both
 // channels as one 16-byte store: half the store requests of one channel per workgroup,
 // whose 8-byte stores each hit their own cache line (the bins of a channel lie L apart).
-// Up to M = 2048 a thread holds 8 points and the kernel fits eight waves per SIMD.  The
-// kernel is persistent: workgroup bid takes channel groups item = bid, bid + G, ... of the
-// L F / CH; once the first pass has put a group into LDS, the next group's samples are
-// loaded into the registers it freed, so those HBM reads overlap the later LDS passes and
-// the bin writes of this one.  Consecutive workgroups go round-robin to the 8 XCDs, so the
+// Up to M = 2048 a thread holds 8 points and the kernel fits eight waves per SIMD.  Workgroup
+// bid takes channel groups item = bid, bid + G, ... of the L F / CH (the host launches one
+// group per workgroup, or fewer workgroups that each walk several); when it walks several,
+// once the first pass has put a group into LDS the next group's samples are loaded into the
+// registers it freed, so those HBM reads overlap the later LDS passes and the bin writes.  Consecutive workgroups go round-robin to the 8 XCDs, so the
 // index is remapped to give each XCD runs of consecutive channel groups of a frame: their
 // bin writes then fill the same cache lines of one L2.
 template <int LOGM, int CH = 1, int EPT = (LOGM <= 11 ? 8 : (1 << LOGM) / 256)>

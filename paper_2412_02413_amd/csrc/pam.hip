@@ -913,13 +913,17 @@ pam_status_t run_groups(pam_plan_t p, const float* rf, const pam_group_t* groups
       if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return false;
-      // persistent: as many workgroups as the device holds at once (each walks its channels)
+      // From 2048 samples one workgroup per channel group (the groups of a frame are resident together, so
+      // their partial bin lines meet in L2: 0.047 vs 0.050 ms for 64 x 128 channels of 4096 samples); shorter
+      // records persistent, as many workgroups as the device holds, each walking its groups with the next
+      // group's samples prefetched (0.011 vs 0.012 ms for 64 x 64 channels of 1024 samples).
       int occ = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kernel), 256 * ch, lds) !=
               hipSuccess ||
           occ < 1)
         return false;
-      const unsigned blocks = (unsigned)std::min<long long>(items, (long long)occ * p->n_cus);
+      const unsigned blocks =
+          (unsigned)(q.n_t >= 2048 ? items : std::min<long long>(items, (long long)occ * p->n_cus));
       hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256 * ch), lds, stream, a);
       return true;
     };

@@ -618,17 +618,26 @@ __global__ void clear_max_kernel(unsigned* fmax, int32_t n) {
   if (k < n) fmax[k] = 0u;
 }
 
+// A workgroup covers kEnergyPix pixels of one frame (16 per thread), so a frame's maximum
+// takes a few dozen atomics on its address rather than one per 256 pixels: same-address
+// atomics are serialised in L2.
+constexpr int kEnergyPix = 256 * 16;
 __global__ __launch_bounds__(256) void energy_max_kernel(const float* acc, int32_t n_split, int64_t sstride,
                                                          int64_t P, float* energy, unsigned* fmax) {
   __shared__ float red[256];
   const int64_t f = blockIdx.y;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * kEnergyPix + threadIdx.x;
   float v = 0.f;
-  if (p < P) {
-    const float* a0 = acc + f * 5 * P + p;
-    for (int s = 0; s < n_split; ++s) v += a0[s * sstride];
-    v = fmaxf(v, 0.f);
-    energy[f * P + p] = v;
+  for (int k = 0; k < 16; ++k) {
+    const int64_t p = p0 + 256 * k;
+    if (p < P) {
+      const float* a0 = acc + f * 5 * P + p;
+      float e = 0.f;
+      for (int s = 0; s < n_split; ++s) e += a0[s * sstride];
+      e = fmaxf(e, 0.f);
+      energy[f * P + p] = e;
+      v = fmaxf(v, e);
+    }
   }
   red[threadIdx.x] = v;
   __syncthreads();
@@ -949,7 +958,8 @@ pam_status_t pam_nn_coherence_features(const float* accum, int32_t n_split, int6
   unsigned* fm = reinterpret_cast<unsigned*>(frame_max);
   const dim3 grid(blocks_for(P, 256), batch);
   hipLaunchKernelGGL(clear_max_kernel, dim3(blocks_for(batch, 256)), dim3(256), 0, st, fm, batch);
-  hipLaunchKernelGGL(energy_max_kernel, grid, dim3(256), 0, st, accum, n_split, split_stride, P, energy, fm);
+  hipLaunchKernelGGL(energy_max_kernel, dim3(blocks_for(P, kEnergyPix), batch), dim3(256), 0, st, accum, n_split,
+                     split_stride, P, energy, fm);
   hipLaunchKernelGGL(coherence_features_kernel, grid, dim3(256), 0, st, accum, n_split, split_stride, n_z, n_x,
                      energy, fm, static_cast<bf16*>(out));
   return launched();
