@@ -329,10 +329,12 @@ def test_resumed_training_follows_the_same_trajectory(env, small_data):
     """A run checkpointed after 4 steps (master weights, Adam moments and step, the batch
     sampler's generator state) and resumed in a fresh network retraces the next 4 losses and
     ends at the same parameters.  The weight gradients sum with atomics, so the agreement
-    is to FP32 rounding, not bit for bit: a parameter may differ by 1e-4 of its tensor's
-    largest magnitude plus 1 % of the most Adam can move it in the 4 resumed steps
-    (lr per step).  Resuming without the moments, the step count or the sampler state moves
-    parameters by O(lr) per step and changes the losses, which both bounds catch."""
+    is to FP32 rounding, not bit for bit.  Adam moves a parameter by about lr per step
+    whatever its gradient's size, so where a gradient is near zero the rounding of the
+    atomic sums can flip an update: single parameters may differ by up to lr per resumed
+    step.  Most of a tensor may not: its mean difference stays under 5 % of lr x steps.
+    Resuming without the moments, the step count or the sampler state shifts most
+    parameters by O(lr) per step (and changes the losses), which the mean bound catches."""
     import copy
     torch, nn, S = env
     g, A, R, _, _ = small_data
@@ -352,6 +354,8 @@ def test_resumed_training_follows_the_same_trajectory(env, small_data):
         for x, y in zip(a[1:], b[1:]):
             assert abs(x - y) <= 1e-4 * max(abs(x), 1e-6), (a, b)
     assert other.step_count == net.step_count == 8
+    lr, steps = 3e-4, 4
     for k in net.params:
-        d = (net.params[k] - other.params[k]).abs().max().item()
-        assert d <= 1e-4 * net.params[k].abs().max().item() + 0.01 * 4 * 3e-4, (k, d)
+        d = (net.params[k] - other.params[k]).abs()
+        assert d.max().item() <= lr * steps + 1e-4 * net.params[k].abs().max().item(), (k, d.max().item())
+        assert d.mean().item() <= 0.05 * lr * steps, (k, d.mean().item())
