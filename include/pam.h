@@ -232,15 +232,17 @@ pam_status_t pam_as_tax_noalloc(pam_plan_t p, const float* rf, int64_t n_frames,
  * of the plan's record lengths, as for pam_as_tax; 1 <= n_groups <= 8, at most 65535 frames
  * in all).  rf (device) holds the groups back to back, group g as
  * [n_frames][L][n_t] after the groups before it; image, nncc (and rho_pairs) hold the
- * frames in the same order.  The workspace (pam_workspace_size_grouped bytes, 256-byte
- * aligned) holds the groups' workspaces back to back, each laid out as
- * pam_workspace_layout would for that group with the bin split chosen over the whole
- * call where the fields stage is one launch (else per group); it serves any group list whose groups, position by position, have no more
- * frames and no longer records.  Stages K1, K2 and K4 run per group; on the factored fields kernels (N_x = 256 or
- * 512, and 128 with FP32 operands) the fields stage runs as one launch over all groups
- * (a grouped work list), otherwise per group.  Results equal pam_as_tax on each group up
- * to FP32 summation order (the bin split depends on the frames of the call).  Errors as
- * pam_as_tax; PAM_ERR_INVALID_ARG for a bad group list. */
+ * frames in the same order.  Stages K1, K2 and K4 run per group.  On the factored fields
+ * kernels (N_x = 256 or 512, and 128 with FP32 operands) the fields stage runs as one launch
+ * over all groups (a grouped work list, one bin split for the call) when the library's cost
+ * estimate of that launch is below the sum of the groups' own launches; otherwise, and on
+ * the other kernels, it runs per group with each group's own split.  The workspace
+ * (pam_workspace_size_grouped bytes, 256-byte aligned) holds the groups' workspaces back to
+ * back, each laid out as pam_workspace_layout would for that group and split; it serves any
+ * group list whose groups, position by position, have no more frames and no longer
+ * records.  Results equal pam_as_tax on each group up to FP32 summation order (the bin split
+ * depends on the frames of the call).  Errors as pam_as_tax; PAM_ERR_INVALID_ARG for a bad
+ * group list. */
 typedef struct {
   int32_t n_t;       /* record length of the group's frames */
   int64_t n_frames;  /* frames in the group (may be 0) */
@@ -261,9 +263,13 @@ const char* pam_status_string(pam_status_t s);
  *   returns PAM_ERR_OOM after releasing what it had allocated; n < 0 disarms.  One
  *   injected failure per call; not meant for use beside concurrent pam_plan calls.
  * pam_debug_live_allocations(): the number of device allocations held by all live plans
- *   of the process (a leak check: unchanged across a failed pam_plan). */
+ *   of the process (a leak check: unchanged across a failed pam_plan).
+ * pam_debug_grouped_one_launch(p, groups, n_groups): 1 if pam_as_tax_grouped with this
+ *   group list runs the fields stage as one grouped launch, 0 if per group, or a negative
+ *   pam_status_t for a bad plan or group list (so tests can cover both schedules). */
 void pam_debug_fail_allocation(int32_t n);
 int64_t pam_debug_live_allocations(void);
+int32_t pam_debug_grouped_one_launch(pam_plan_t p, const pam_group_t* groups, int32_t n_groups);
 
 #ifdef __cplusplus
 }

@@ -454,7 +454,10 @@ struct K3Groups {
 __device__ __forceinline__ int wg_group(K3Args& a, const K3Groups& grp) {
   const int G = gridDim.x;
   int bid = blockIdx.x;
-  if ((G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
+  // One frame batch: each XCD takes a contiguous eighth of the workgroups, so the tiles of a frame share one
+  // L2.  A grouped launch keeps the hardware's round-robin order instead, so that every XCD gets the same mix
+  // of the groups' (unequal) workgroups.
+  if ((G & 7) == 0 && grp.n <= 1) bid = (bid & 7) * (G >> 3) + (bid >> 3);
   if (grp.n > 0) {
     int g = 0;
     while (g + 1 < grp.n && bid >= grp.g[g + 1].wg_begin) ++g;

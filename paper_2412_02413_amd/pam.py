@@ -97,6 +97,8 @@ def _lib():
         lib.pam_as_tax_grouped.restype = C.c_int
         lib.pam_debug_fail_allocation.argtypes = [i32]
         lib.pam_debug_fail_allocation.restype = None
+        lib.pam_debug_grouped_one_launch.argtypes = [vp, vp, i32]
+        lib.pam_debug_grouped_one_launch.restype = C.c_int32
         lib.pam_debug_live_allocations.argtypes = []
         lib.pam_debug_live_allocations.restype = i64
         _LIB = lib
@@ -232,6 +234,14 @@ def debug_fail_allocation(n: int) -> None:
 def debug_live_allocations() -> int:
     """Device allocations held by all live plans of the process."""
     return int(_lib().pam_debug_live_allocations())
+
+
+def debug_grouped_one_launch(plan: Plan, groups) -> bool:
+    """Whether pam_as_tax_grouped with these (n_t, n_frames) groups runs its fields stage as
+    one grouped launch (else one launch per group)."""
+    r = int(_lib().pam_debug_grouped_one_launch(C.c_void_p(plan.handle), _groups(groups), len(groups)))
+    _check(min(r, 0), "pam_debug_grouped_one_launch")
+    return r == 1
 
 
 def pam_destroy(plan: Plan) -> None:

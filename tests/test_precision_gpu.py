@@ -108,7 +108,8 @@ def test_grouped_call_mixes_record_lengths(env, precision):
     samples back to back, with an empty group in between): every frame equals the per-length
     call on the same frames up to summation order, and the first frame of each length
     matches the FP64 oracle at the form's tolerance.  In FP32 the fields stage is one grouped
-    work-list launch over all lengths."""
+    work-list launch over all lengths when its cost estimate beats per-length launches (not
+    for these 64 frames: each length fills the device on its own)."""
     torch, pam = env
     g = synth.cfg3_geometry()
     frames = [synth.cfg3_frame(s) for s in range(64)]
@@ -123,6 +124,7 @@ def test_grouped_call_mixes_record_lengths(env, precision):
         img = torch.empty((F, g.n_z, g.n_x), device="cuda")
         rho = torch.empty_like(img)
         ws = pam.alloc_workspace_grouped(plan, groups)
+        assert not pam.debug_grouped_one_launch(plan, groups)
         pam.pam_as_tax_grouped(plan, rf, groups, img, rho, None, ws)
         torch.cuda.synchronize()
         img, rho = img.cpu().numpy().astype(np.float64), rho.cpu().numpy().astype(np.float64)
@@ -146,3 +148,39 @@ def test_grouped_call_mixes_record_lengths(env, precision):
               f"max|d rho_n|={e_r:.3e}", flush=True)
         assert e_i <= tol_i and e_r <= tol_r
         k += len(idx)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_grouped_work_list_launch(env, precision):
+    """One frame of each record length on a shallow grid (33 depths: two depth tiles a frame
+    at 128 columns in FP32): no length fills the device alone, so the fields stage runs as ONE
+    grouped work-list launch (FP32; the split form at 128 columns runs per length).  Every
+    frame equals its per-length call up to summation order and the FP64 oracle at the form's
+    tolerance."""
+    torch, pam = env
+    g = synth.cfg3_geometry().replace(depths_m=(20 + 0.5 * np.arange(33)) * MM)
+    rng = np.random.default_rng(21)
+    em = [synth.Emitter(1 * MM, 30 * MM, "broadband"), synth.Emitter(-4 * MM, 26 * MM, "stable")]
+    lengths = [2048, 4096, 8192]
+    frames = {n: synth.render(g, em, rng, n_t=n)[None] for n in lengths}
+    groups = [(n, 1) for n in lengths]
+    plan = pam.pam_plan(g, 0, precision)
+    try:
+        assert pam.debug_grouped_one_launch(plan, groups) == (precision == "fp32")
+        rf = torch.from_numpy(np.concatenate([frames[n].ravel() for n in lengths]).astype(np.float32)).cuda()
+        img = torch.empty((3, g.n_z, g.n_x), device="cuda")
+        rho = torch.empty_like(img)
+        ws = pam.alloc_workspace_grouped(plan, groups)
+        pam.pam_as_tax_grouped(plan, rf, groups, img, rho, None, ws)
+        torch.cuda.synchronize()
+        img, rho = img.cpu().numpy().astype(np.float64), rho.cpu().numpy().astype(np.float64)
+    finally:
+        pam.pam_destroy(plan)
+    tol_i, tol_r = (1e-5, 1e-4) if precision == "fp32" else (1e-3, 1e-3)
+    for k, n in enumerate(lengths):
+        alone_i, alone_r = gpu_run(env, g, frames[n], precision)
+        e = float(np.linalg.norm(img[k] - alone_i[0]) / np.linalg.norm(alone_i[0]))
+        assert e <= 1e-5 and float(np.abs(rho[k] - alone_r[0]).max()) <= 1e-4, (n, e)
+        e_i, e_r = errors(img[k], rho[k], O.as_tax(frames[n][0], g.replace(n_samples=n)))
+        print(f"{precision} n_t={n}: grouped vs oracle relL2(I)={e_i:.3e} max|d rho_n|={e_r:.3e}", flush=True)
+        assert e_i <= tol_i and e_r <= tol_r
