@@ -279,25 +279,27 @@ int k3_bin_cap(const pam_plan_s* p, const int64_t* F, const int* n_sel, int n, d
   const double plane_cost = (double)n_acc(p->n_sub, p->coherence) * p->n_z * p->N * 4.0 / 4e12 / 5e-6;
   // The estimate is constant between the caps where some group's split count changes, so it is evaluated at the
   // top of each such piece: for every group g and split count s, the largest cap that splits g s ways
-  // (n_g for s = 1, ceil(n_g / (s - 1)) - 1 after), in decreasing order.  This equals trying every cap.
+  // (n_g for s = 1, ceil(n_g / (s - 1)) - 1 after), in decreasing order (a merge over the groups' sequences,
+  // no storage).  This equals trying every cap.
   const int min_b = std::min(8, max_n);
-  std::vector<int> caps;
+  auto top = [&](int g, int s) { return s == 1 ? n_sel[g] : (n_sel[g] + s - 2) / (s - 1) - 1; };
+  int next_s[pam::kMaxGroups];
+  int live = 0;
   for (int g = 0; g < n; ++g) {
-    if (F[g] == 0 || n_sel[g] == 0) continue;
-    for (int s = 1;; ++s) {
-      const int b = s == 1 ? n_sel[g] : (n_sel[g] + s - 2) / (s - 1) - 1;
-      if (b < min_b) break;
-      caps.push_back(b);
-    }
+    next_s[g] = 1;
+    live += F[g] > 0 && n_sel[g] > 0;
   }
-  caps.push_back(max_n);
-  std::sort(caps.begin(), caps.end(), std::greater<int>());
-  caps.erase(std::unique(caps.begin(), caps.end()), caps.end());
   double best = 0;
   int best_b = max_n;
-  int live = 0;
-  for (int g = 0; g < n; ++g) live += F[g] > 0 && n_sel[g] > 0;
-  for (const int b : caps) {
+  for (bool first = true;; first = false) {
+    int b = -1;
+    for (int g = 0; g < n; ++g)
+      if (F[g] > 0 && n_sel[g] > 0) b = std::max(b, top(g, next_s[g]));
+    if (first) b = max_n;
+    if (b < min_b) break;
+    for (int g = 0; g < n; ++g)      // step every group past this cap
+      if (F[g] > 0 && n_sel[g] > 0)
+        while (top(g, next_s[g]) >= b) ++next_s[g];
     int64_t n_wg = 0;
     int job = 0;
     double k4 = 0, work = 0;
