@@ -830,7 +830,7 @@ namespace {
 // group with frames, and the cost estimate of that launch below the sum of the groups' own launches); cap[g]:
 // group g's bins-per-workgroup cap, the shared one for a grouped launch, else the group's own.
 pam_status_t grouped_layout(const pam_plan_s* p, const pam_group_t* groups, int n_groups,
-                            std::vector<pam_workspace_layout_t>& W, std::vector<size_t>& base, size_t* total,
+                            pam_workspace_layout_t* W, size_t* base, size_t* total,
                             int* cap, bool* one_launch) {
   if (n_groups < 1 || n_groups > pam::kMaxGroups || !groups) return PAM_ERR_INVALID_ARG;
   int64_t F_total = 0;
@@ -862,8 +862,6 @@ pam_status_t grouped_layout(const pam_plan_s* p, const pam_group_t* groups, int 
       for (int g = 0; g < n_groups; ++g) cap[g] = shared;
     }
   }
-  W.resize(n_groups);
-  base.resize(n_groups);
   size_t o = 0;
   for (int g = 0; g < n_groups; ++g) {
     const pam_status_t st = layout(p, groups[g].n_frames, groups[g].n_t, &W[g], cap[g]);
@@ -882,8 +880,9 @@ pam_status_t run_groups(pam_plan_t p, const float* rf, const pam_group_t* groups
                         float* nncc, float* rho_pairs, void* workspace, size_t ws_bytes, void* hip_stream,
                         void* const* events, int method) {
   if (!p) return PAM_ERR_INVALID_ARG;
-  std::vector<pam_workspace_layout_t> W;
-  std::vector<size_t> wbase;
+  // per group, fixed arrays of at most kMaxGroups entries: the call allocates no host memory either
+  pam_workspace_layout_t W[pam::kMaxGroups];
+  size_t wbase[pam::kMaxGroups];
   size_t total = 0;
   int cap[pam::kMaxGroups];
   bool one_launch = false;
@@ -916,7 +915,7 @@ pam_status_t run_groups(pam_plan_t p, const float* rf, const pam_group_t* groups
     float *scales, *accum, *energy, *weight, *blockmax;
     LaunchShape s;
   };
-  std::vector<G> gs(n_groups);
+  G gs[pam::kMaxGroups] = {};
   {
     size_t rf_off = 0, out_off = 0;
     for (int g = 0; g < n_groups; ++g) {
@@ -1091,11 +1090,11 @@ pam_status_t run_groups(pam_plan_t p, const float* rf, const pam_group_t* groups
     return PAM_OK;
   }
   // stage after stage (one group, with the stage marks, or one grouped fields launch)
-  for (const G& q : gs)
-    if ((st = stage_k1(q)) != PAM_OK) return st;
+  for (int g = 0; g < n_groups; ++g)
+    if ((st = stage_k1(gs[g])) != PAM_OK) return st;
   if (!mark(1)) return PAM_ERR_DEVICE;
-  for (const G& q : gs)
-    if ((st = stage_k2(q)) != PAM_OK) return st;
+  for (int g = 0; g < n_groups; ++g)
+    if ((st = stage_k2(gs[g])) != PAM_OK) return st;
   if (!mark(2)) return PAM_ERR_DEVICE;
   if (method == 0 && one_launch) {
     // one launch over every group: a grouped work list on the factored kernels
@@ -1103,12 +1102,15 @@ pam_status_t run_groups(pam_plan_t p, const float* rf, const pam_group_t* groups
     long long blocks = 0;
     const G* first = nullptr;
     // the work list runs the groups with the longest workgroups first (a short tail)
-    std::vector<const G*> order;
-    for (const G& q : gs)
-      if (q.F > 0) order.push_back(&q);
-    std::stable_sort(order.begin(), order.end(),
-                     [](const G* x, const G* y) { return x->s.bins_per_split > y->s.bins_per_split; });
-    for (const G* qp : order) {
+    const G* order[pam::kMaxGroups];
+    int n_order = 0;
+    for (int g = 0; g < n_groups; ++g)
+      if (gs[g].F > 0) order[n_order++] = &gs[g];
+    for (int k = 1; k < n_order; ++k)      // stable insertion sort, longest workgroups first (no buffer)
+      for (int m = k; m > 0 && order[m - 1]->s.bins_per_split < order[m]->s.bins_per_split; --m)
+        std::swap(order[m - 1], order[m]);
+    for (int k = 0; k < n_order; ++k) {
+      const G* qp = order[k];
       const G& q = *qp;
       if (!first) first = &q;
       pam::K3Group& e = grp.g[grp.n++];
@@ -1121,8 +1123,8 @@ pam_status_t run_groups(pam_plan_t p, const float* rf, const pam_group_t* groups
         hipSuccess)
       return PAM_ERR_DEVICE;
   } else {
-    for (const G& q : gs)
-      if ((st = stage_k3(q)) != PAM_OK) return st;
+    for (int g = 0; g < n_groups; ++g)
+      if ((st = stage_k3(gs[g])) != PAM_OK) return st;
   }
   if (!mark(3)) return PAM_ERR_DEVICE;
   for (int g = 0; g < n_groups; ++g)
@@ -1167,8 +1169,8 @@ void pam_destroy(pam_plan_t p) { free_plan(p); }
 
 pam_status_t pam_workspace_size_grouped(pam_plan_t p, const pam_group_t* groups, int32_t n_groups, size_t* bytes) {
   if (!p || !bytes) return PAM_ERR_INVALID_ARG;
-  std::vector<pam_workspace_layout_t> W;
-  std::vector<size_t> base;
+  pam_workspace_layout_t W[pam::kMaxGroups];
+  size_t base[pam::kMaxGroups];
   int cap[pam::kMaxGroups];
   bool one_launch = false;
   return grouped_layout(p, groups, n_groups, W, base, bytes, cap, &one_launch);
@@ -1186,8 +1188,8 @@ int64_t pam_debug_live_allocations(void) { return g_live_allocs.load(); }
 
 int32_t pam_debug_grouped_one_launch(pam_plan_t p, const pam_group_t* groups, int32_t n_groups) {
   if (!p) return PAM_ERR_INVALID_ARG;
-  std::vector<pam_workspace_layout_t> W;
-  std::vector<size_t> base;
+  pam_workspace_layout_t W[pam::kMaxGroups];
+  size_t base[pam::kMaxGroups];
   size_t total = 0;
   int cap[pam::kMaxGroups];
   bool one_launch = false;
