@@ -50,11 +50,12 @@ template <int NN>
 __host__ __device__ constexpr int ft_depths() { return NN == 128 ? 32 : (NN == 256 ? 16 : 8); }
 
 // LDS: staged bins [2][ff_stage_rows], stage twiddles [16 x1][16 j], (N = 512) combination
-// twiddles [16 x2][16 j], transpose blocks [4 waves][4 groups][kFtTr].
+// twiddles [2 e][16 x2][16 j], transpose blocks [4 waves][4 groups][kFtTr].
+template <int NN>
+__host__ __device__ constexpr int ft_twiddles() { return NN == 512 ? 768 : 256; }
 template <int NSUB, int NN = 256>
 inline size_t k3fft_lds() {
-  return (size_t)(2 * ff_stage_rows<NSUB, NN / 16>() + (NN == 512 ? 512 : 256) + kFtWaves * 4 * kFtTr) *
-         sizeof(float2);
+  return (size_t)(2 * ff_stage_rows<NSUB, NN / 16>() + ft_twiddles<NN>() + kFtWaves * 4 * kFtTr) * sizeof(float2);
 }
 
 // The 16-byte pieces of a bin's staged inputs, 256 per pass (one per thread): one pass at
@@ -217,11 +218,11 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
   constexpr int ROWS = NN / 16;
   extern __shared__ float2 lds_ft[];
   float2* stage = lds_ft;                                          // [2][ff_stage_rows]
-  float2* twl = lds_ft + 2 * ff_stage_rows<NSUB, ROWS>();          // [16 x1][16 j] (+ [16 x2][16 j])
+  float2* twl = lds_ft + 2 * ff_stage_rows<NSUB, ROWS>();          // [16 x1][16 j] (+ [2 e][16 x2][16 j])
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int g = lane >> 4, j = lane & 15;
   const int e = R == 2 ? (g & 1) : 0;                              // parity of q (N = 512)
-  float2* tr = twl + 256 * R + (w * 4 + g) * kFtTr;                // this group's transpose block
+  float2* tr = twl + ft_twiddles<NN>() + (w * 4 + g) * kFtTr;     // this group's transpose block
   // staged row of this lane's stage-1 inputs
   const int srow = HALF ? (j & 7) : (R == 1 ? j : 2 * j + e);
   K3Args a = a0;
@@ -233,9 +234,12 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
   const int depth1 = HALF ? depth + (j >> 3) : depth;
   const double z = depth1 < a.n_z ? a.z[depth1] : 0.0;
 
-  // stage-1 -> stage-3 twiddles e^{2 pi i q2 x1 / 256} and (N = 512) the combination
-  // twiddles e^{2 pi i (j + 16 x2) / 512} (FP32 tables built in FP64)
-  for (int k = tid; k < 256 * R; k += 256) twl[k] = k < 256 ? a.ff_tw_vec[k] : a.ff_tw2_vec[k - 256];
+  // stage-1 -> stage-3 twiddles e^{2 pi i q2 x1 / 256} and (N = 512) the combination twiddles
+  // e^{2 pi i (j + 16 x2 + 256 e) / 512}, the e = 1 half the negated e = 0 half (FP32 tables built in FP64)
+  for (int k = tid; k < ft_twiddles<NN>(); k += 256) {
+    const float2 t = k < 256 ? a.ff_tw_vec[k] : a.ff_tw2_vec[(k - 256) & 255];
+    twl[k] = k < 512 ? t : make_float2(-t.x, -t.y);
+  }
 
   float accS[NSUB][16];
   float accC[NP > 0 ? NP : 1][16];
@@ -268,11 +272,12 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
     // propagator at q = 16 m + j (N = 256) or 32 m + 2 j + e (N = 512) (Eq. 2): phase in FP64 reduced to [-1/2, 1/2] cycle,
     // hardware sin/cos; evanescent values replaced in a branch only lanes holding any take.
     // kz(q) = kz(N - q).  At N = 256, N - (16 m + j) = 16 (15 - m) + (16 - j): lane j's H[m] for m > 8 is lane
-    // (16 - j)'s H[15 - m] (same depth), and lane 0's is its own H[16 - m].  At N = 128 (q = 8 m + q2, q2 = j % 8,
-    // one depth per 8 lanes) the partner of q2 is 8 - q2 in the same 8 lanes, and q2 = 0 pairs with itself.  So a
-    // lane computes H[0..8] and takes the other seven from its partner lane.
-    constexpr bool SYM = NN == 256 || NN == 128;
-    constexpr int MD = SYM ? 9 : 16;   // values computed directly
+    // (16 - j)'s H[15 - m] (same depth), and lane 0's is its own H[16 - m].  At N = 512 the even-q rows (e = 0)
+    // pair the same way, N - (32 m + 2 j) = 32 (15 - m) + 2 (16 - j), and in the odd-q rows
+    // N - (32 m + 2 j + 1) = 32 (15 - m) + 2 (15 - j) + 1 pairs lane j with lane 15 - j, none with itself.  At
+    // N = 128 (q = 8 m + q2, q2 = j % 8, one depth per 8 lanes) the partner of q2 is 8 - q2 in the same 8 lanes,
+    // and q2 = 0 pairs with itself.  So a lane computes H[0..8] and takes the other seven from its partner lane.
+    constexpr int MD = 9;   // values computed directly
     float2 H[16];
 #pragma unroll
     for (int m = 0; m < MD; ++m) {
@@ -285,12 +290,14 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
       for (int m = 0; m < MD; ++m)
         if (kzr[m] < 0.0) H[m] = propagator(z, kzr[m], a.zero_evanescent);
     }
-    if constexpr (SYM) {
-      const bool self = (HALF ? (j & 7) : j) == 0;
+    {
+      const bool self = (HALF ? (j & 7) : j) == 0 && e == 0;
 #pragma unroll
       for (int m = MD; m < 16; ++m) {
-        const float2 o = HALF ? make_float2(lane_mirror8(H[15 - m].x), lane_mirror8(H[15 - m].y))
-                              : make_float2(lane_mirror16(H[15 - m].x), lane_mirror16(H[15 - m].y));
+        const float2 o =
+            HALF     ? make_float2(lane_mirror8(H[15 - m].x), lane_mirror8(H[15 - m].y))
+            : R == 2 ? make_float2(lane_mirror16_odd_rows15(H[15 - m].x), lane_mirror16_odd_rows15(H[15 - m].y))
+                     : make_float2(lane_mirror16(H[15 - m].x), lane_mirror16(H[15 - m].y));
         H[m] = self ? H[16 - m] : o;
       }
     }
@@ -326,13 +333,15 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
         idft16(p[i]);                                              // p(j + 16 x2), x2 = 0..15
       }
       if constexpr (R == 2) {
-        // P_0 +- w P_1: group parity e = 0 holds P_0(x'), e = 1 P_1(x'), x' = j + 16 x2
+        // p(x' + 256 e) = P_0(x') + w P_1(x'), x' = j + 16 x2, w = e^{2 pi i (x' + 256 e) / 512}: the even row of
+        // each row pair (e = 0) holds P_0(x'), the odd row P_1(x'), and one row swap hands both to both rows
 #pragma unroll
         for (int x2 = 0; x2 < 16; ++x2) {
-          const float2 o = make_float2(lane_xor16(p[i][x2].x), lane_xor16(p[i][x2].y));
-          const float2 p0 = e ? o : p[i][x2], p1 = e ? p[i][x2] : o;
-          const float2 t = cmul(twl[256 + x2 * 16 + j], p1);
-          p[i][x2] = e ? f2sub(p0, t) : f2add(p0, t);
+          const float2 re = rows_even_odd(p[i][x2].x), im = rows_even_odd(p[i][x2].y);   // (P_0, P_1) parts
+          const float2 w2 = twl[256 + 256 * e + x2 * 16 + j];
+          p[i][x2] = make_float2(fmaf(w2.x, re.y, fmaf(-w2.y, im.y, re.x)), fmaf(w2.x, im.y, fmaf(w2.y, re.y, im.x)));
+          // combined here: sunk to the fold, the two swapped halves would stay live instead of the result
+          asm volatile("" : "+v"(p[i][x2].x), "+v"(p[i][x2].y));
         }
         if (i == 0 && more) {
           pc.store(nxt, 0);

@@ -99,6 +99,24 @@ __device__ __forceinline__ float lane_mirror16(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(t, 0x140, 0xF, 0xF, false));
 }
 
+// Rows 0 and 2 of the wave: the value lane (16 - i) mod 16 of the row holds, as lane_mirror16; rows 1 and 3: the
+// value lane 15 - i holds.  The rotation is written to rows 0 and 2 only (DPP row mask 0b0101; the other rows keep
+// their own values), then every row is mirrored.
+__device__ __forceinline__ float lane_mirror16_odd_rows15(float v) {
+  const int x = __builtin_bit_cast(int, v);
+  const int t = __builtin_amdgcn_update_dpp(x, x, 0x12F, 0x5, 0xF, false);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(t, 0x140, 0xF, 0xF, false));
+}
+
+// Rows 2r and 2r + 1 of the wave as a pair: every lane i of both rows receives lane i of the even row in .x and
+// lane i of the odd row in .y (v_permlane16_swap of a register with itself swaps the odd row of the first
+// operand with the even row of the second).
+__device__ __forceinline__ float2 rows_even_odd(float v) {
+  const unsigned u = __builtin_bit_cast(unsigned, v);
+  const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return make_float2(__builtin_bit_cast(float, (unsigned)r[0]), __builtin_bit_cast(float, (unsigned)r[1]));
+}
+
 // The value lane (8 - i) mod 8 of the lane's group of 8 holds (i = lane index in the group), for i = 1..7: the
 // row rotation by 15 (lane i takes lane i + 1 mod 16) followed by a DPP half-row mirror (lane i takes lane 7 - i
 // of its 8).  Lane 0 of each group receives a value from outside its group; callers use it only for i > 0.
