@@ -744,9 +744,6 @@ def main():
     if pshape:
         log(f"paper shape: {pshape}")
     serving = serving_entry(args.precision, args.serving_horizon) if args.serving_horizon > 0 else None
-    if serving is not None and args.precision == "fp32":
-        # the same mix with the fastest form at the FP32 tolerances per array (split FP16 at 512 columns)
-        serving["auto_precision"] = serving_entry("auto", args.serving_horizon, loads=(1000.0, 5000.0))
     evaluation = None
     if args.evaluation:
         from paper_2412_02413_amd import evaluate as EV

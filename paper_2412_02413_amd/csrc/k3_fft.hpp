@@ -343,7 +343,8 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
           // combined here: sunk to the fold, the two swapped halves would stay live instead of the result
           asm volatile("" : "+v"(p[i][x2].x), "+v"(p[i][x2].y));
         }
-        if (i == 0 && more) {
+        // the next bin's second half once every transform is done (fewer values live through the transforms)
+        if (i == NSUB - 1 && more) {
           pc.store(nxt, 0);
           pc.load(a, f, b + 1, tid, 1);
         }

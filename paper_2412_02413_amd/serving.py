@@ -87,20 +87,10 @@ class Server:
     def geometry(self, key: ArrayKey):
         return synth.cfg5_geometry(key.n_elements, key.fs_hz, self.max_samples)
 
-    def precision_for(self, key: ArrayKey) -> str:
-        """The operand form of a plan.  precision="auto" picks the fastest form that meets the
-        FP32 tolerances for the array's grid: FP32 on the vector-FFT kernel up to 256 columns,
-        split FP16 on the matrix cores at 512 columns (where the FP32 kernel runs out of
-        registers; tests/test_serving_gpu.py checks split FP16 against the FP64 oracle at
-        the FP32 tolerances on that grid)."""
-        if self.precision != "auto":
-            return self.precision
-        return "split_fp16" if self.geometry(key).n_x >= 512 else "fp32"
-
     def plan(self, key: ArrayKey) -> pam.Plan:
         p = self.plans.get(key)
         if p is None:
-            p = pam.pam_plan(self.geometry(key), self.dev_index, self.precision_for(key))
+            p = pam.pam_plan(self.geometry(key), self.dev_index, self.precision)
             self.plans[key] = p
         return p
 
@@ -278,7 +268,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="Poisson load test of the continuous-batching server")
     ap.add_argument("--loads", default="100,1000,5000")
     ap.add_argument("--requests", type=int, default=300, help="requests per offered load")
-    ap.add_argument("--precision", default="fp32", help="operand form, or auto (FP32 tolerances, fastest per array)")
+    ap.add_argument("--precision", default="fp32")
     ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--hbm-gib", type=float, default=32.0)

@@ -342,7 +342,7 @@ def test_factored_transform_forms(pam, torch_cuda, precision, n_sub):
         check_end_to_end(res, O.as_tax(rf[f], g), f, tol_i=tol_i, tol_rho=tol_rho)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16", "split_fp16"])
 def test_largest_serving_frame(pam, torch_cuda, precision):
     """The largest serving frame's array and record: 256 elements at 0.2 mm on 512 columns,
     16384 samples at 20 MHz.  A 159-bin band (2.0-2.195 MHz) and 32 depths keep the oracle

@@ -65,35 +65,3 @@ def test_budget_admission_and_rejection(env):
     finally:
         srv.close()
 
-
-def test_auto_precision_picks_split_fp16_at_512_columns(env):
-    """precision="auto" serves the 256-element array (512 columns) in split FP16 and the others
-    in FP32; split FP16 on that grid meets the FP32 tolerances against the FP64 oracle (1e-5 on
-    the image, 1e-4 on the NNCC): 256 elements at 0.2 mm, 1024 samples, 21 depths."""
-    torch, pam, serving, pool = env
-    from oracle import as_tax as O
-    from paper_2412_02413_amd import synth
-    srv = serving.Server(precision="auto", max_samples=1024)
-    try:
-        assert srv.precision_for(serving.ArrayKey(256, 40e6)) == "split_fp16"
-        assert srv.precision_for(serving.ArrayKey(128, 40e6)) == "fp32"
-        assert srv.precision_for(serving.ArrayKey(64, 20e6)) == "fp32"
-    finally:
-        srv.close()
-    g = synth.cfg5_geometry(256, 40e6, 1024)
-    g = g.replace(depths_m=g.depths_m[::48][:21])
-    rng = np.random.default_rng(512)
-    em = synth._random_emitters(rng, 3, (-20, 20), (20, 60), [])
-    rf = synth.render(g, em, rng, n_t=1024, snr_db=20.0)
-    plan = pam.pam_plan(g, 0, "split_fp16")
-    try:
-        out = pam.reconstruct(plan, torch.from_numpy(rf[None]).cuda())
-        torch.cuda.synchronize()
-        img, rho = out["image"][0].cpu().numpy(), out["nncc"][0].cpu().numpy()
-    finally:
-        pam.pam_destroy(plan)
-    ref = O.as_tax(rf, g)
-    e_i = float(np.linalg.norm(img - ref["I"]) / np.linalg.norm(ref["I"]))
-    e_r = float(np.abs(rho - ref["rho_n"]).max())
-    print(f"split FP16, 512 columns: relL2(I)={e_i:.2e} max|d rho_n|={e_r:.2e}", flush=True)
-    assert e_i <= 1e-5 and e_r <= 1e-4
