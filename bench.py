@@ -291,9 +291,9 @@ def run_frames(pam, torch, geom, rf_np, precision, dev):
 def mixed_lengths(pam, torch, precisions, steps, dev):
     """64 frames of the 64-element array with record lengths drawn from 2048/4096/8192 on one
     8192-sample plan (the bins of a record are every 2nd / 4th bin of the plan's), timed over
-    all 64 frames as ONE grouped call (pam_as_tax_grouped: the frames packed by record length,
-    the fields stage one work-list launch on the factored kernels) and, for comparison, as
-    one pam_as_tax call per record length."""
+    all 64 frames as ONE grouped call (pam_as_tax_grouped: the frames packed by record length;
+    the library runs the fields stage as one work-list launch where its cost estimate favours
+    that, else group after group) and, for comparison, as one pam_as_tax call per record length."""
     from paper_2412_02413_amd import synth
     g = synth.cfg3_geometry()
     frames = [synth.cfg3_frame(s) for s in range(64)]
@@ -326,16 +326,22 @@ def mixed_lengths(pam, torch, precisions, steps, dev):
                     im, nc, w = bufs[n]
                     pam.pam_as_tax(plan, x, im, nc, None, w, stream, n)
 
-            res = {}
-            for name, fn in (("grouped", grouped), ("per_length_calls", per_length)):
-                fn()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(steps):
+            # two rounds in alternating order, the faster of each form's two timings: neither form
+            # always runs first (clock ramp, caches)
+            best = {}
+            for order in ((("grouped", grouped), ("per_length_calls", per_length)),
+                          (("per_length_calls", per_length), ("grouped", grouped))):
+                for name, fn in order:
                     fn()
-                torch.cuda.synchronize()
-                wall = time.perf_counter() - t0
-                res[name] = {"frames_per_s": round(64 * steps / wall, 2), "ms_per_64_frames": round(1e3 * wall / steps, 3)}
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(steps):
+                        fn()
+                    torch.cuda.synchronize()
+                    wall = time.perf_counter() - t0
+                    best[name] = min(best.get(name, wall), wall)
+            res = {name: {"frames_per_s": round(64 * steps / wall, 2), "ms_per_64_frames": round(1e3 * wall / steps, 3)}
+                   for name, wall in best.items()}
             out[prec] = {**res["grouped"], "per_length_calls": res["per_length_calls"]}
             # first frame of each record length, from the grouped call (packed order)
             k, fr = 0, {}
