@@ -44,7 +44,9 @@ pam_status_t pam_nn_conv3x3(const void* x, int32_t ldx, int32_t batch, int32_t h
                             int32_t relu, int32_t flip, int32_t accumulate, void* hip_stream);
 
 /* dW[t][c][o] += sum_pixels x[p + off(t)][c] * dy[p][o]; db[o] += sum_p dy[p][o] (db nullable).
- * dw (FP32 [9][c_in][c_out]) and db are accumulated with atomics: zero them first. */
+ * dw (FP32 [9][c_in][c_out]) and db are accumulated with atomics: zero them first.
+ * x and dy 16-byte aligned, ldx and lddy multiples of 8 (else PAM_ERR_INVALID_ARG); the
+ * products run on the matrix cores (BF16 operands, FP32 sums). */
 pam_status_t pam_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_t lddy, int32_t batch,
                                   int32_t h, int32_t w, int32_t c_in, int32_t c_out, float* dw, float* db,
                                   void* hip_stream);

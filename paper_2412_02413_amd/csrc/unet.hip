@@ -190,10 +190,16 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient: one workgroup per (32 input channels, 32 output channels,
-// tap, pixel chunk).  Tiles of 64 pixels of x (shifted by the tap) and dy are
-// staged in LDS as FP32; each thread accumulates a 2x2 block of (c, o) over the
-// chunk and adds it to dW with one atomic per value.
+// Weight gradient on v_mfma_f32_32x32x16_bf16: dW[t] = X_t^T dY, a GEMM whose K runs
+// over pixels.  One workgroup per (32 input channels, 32 output channels, tap, pixel
+// chunk).  Per slab of 256 pixels the workgroup stages x (shifted by the tap; zeros
+// outside the image and past the chunk) and dy in LDS transposed, [32 channels][256
+// pixels + 8] BF16, so that an operand fragment (8 consecutive pixels of one channel)
+// is one 16-byte read.  Wave w takes pixels 64 w .. 64 w + 63 of the slab: four
+// products of K = 16 into one 32 x 32 FP32 tile.  At the end the four waves' tiles are
+// summed in LDS and each thread adds four values to dW with atomics.  The products of
+// two BF16 values are exact in FP32, so only the accumulation order differs from an
+// FP32 sum of the same BF16 operands.
 // ---------------------------------------------------------------------------
 struct WgradArgs {
   const bf16* x;
@@ -203,53 +209,66 @@ struct WgradArgs {
   int32_t ldx, lddy, h, w, c_in, c_out;
 };
 
+constexpr int kWgSlab = 256;              // pixels per staged slab
+constexpr int kWgPitch = kWgSlab + 8;     // BF16 per staged channel row (16-byte aligned rows)
+
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
-  __shared__ float xs[64][33];
-  __shared__ float ds[64][33];
+  __shared__ __align__(16) bf16 xt[32 * kWgPitch];
+  __shared__ __align__(16) bf16 dt[32 * kWgPitch];
   const int c0 = blockIdx.x * 32, o0 = blockIdx.y * 32;
   const int t = blockIdx.z % 9;
   const int64_t chunk = blockIdx.z / 9;
   const int dh = t / 3 - 1, dw = t % 3 - 1;
-  const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
-  float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i = lane & 31, half = lane >> 5;
+  const int q = tid & 3;                  // channels 8 q .. 8 q + 7 of the thread's pieces
   const int64_t pbeg = chunk * a.chunk;
   const int64_t pend = min(a.P, pbeg + a.chunk);
-  for (int64_t pr = pbeg; pr < pend; pr += 64) {
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int j = e >> 5, c = e & 31;
+  v16f C;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) C[v] = 0.f;
+  for (int64_t pr = pbeg; pr < pend; pr += kWgSlab) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = (tid >> 2) + 64 * r;   // slab pixel of piece tid + 256 r
       const int64_t p = pr + j;
-      float xv = 0.f, dv = 0.f;
+      v8bf xv = {}, dv = {};
       if (p < pend) {
         const int wc = (int)(p % a.w);
-        const int64_t r = p / a.w;
-        const int hr = (int)(r % a.h);
-        const int64_t img = r / a.h;
+        const int64_t rr = p / a.w;
+        const int hr = (int)(rr % a.h);
+        const int64_t img = rr / a.h;
         const int hh = hr + dh, ww = wc + dw;
         if (hh >= 0 && hh < a.h && ww >= 0 && ww < a.w)
-          xv = (float)a.x[((img * a.h + hh) * a.w + ww) * (int64_t)a.ldx + c0 + c];
-        dv = (float)a.dy[p * (int64_t)a.lddy + o0 + c];
+          xv = *reinterpret_cast<const v8bf*>(a.x + ((img * a.h + hh) * a.w + ww) * (int64_t)a.ldx + c0 + 8 * q);
+        dv = *reinterpret_cast<const v8bf*>(a.dy + p * (int64_t)a.lddy + o0 + 8 * q);
       }
-      xs[j][c] = xv;
-      ds[j][c] = dv;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        xt[(8 * q + k) * kWgPitch + j] = xv[k];
+        dt[(8 * q + k) * kWgPitch + j] = dv[k];
+      }
     }
     __syncthreads();
-#pragma unroll 4
-    for (int j = 0; j < 64; ++j) {
-      const float x0 = xs[j][2 * ty], x1 = xs[j][2 * ty + 1];
-      const float d0 = ds[j][2 * tx], d1 = ds[j][2 * tx + 1];
-      acc[0][0] = fmaf(x0, d0, acc[0][0]);
-      acc[0][1] = fmaf(x0, d1, acc[0][1]);
-      acc[1][0] = fmaf(x1, d0, acc[1][0]);
-      acc[1][1] = fmaf(x1, d1, acc[1][1]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k0 = 64 * wv + 16 * s + 8 * half;   // A[c = i][k0 .. k0 + 7], B[k0 .. k0 + 7][o = i]
+      const v8bf av = *reinterpret_cast<const v8bf*>(xt + i * kWgPitch + k0);
+      const v8bf bv = *reinterpret_cast<const v8bf*>(dt + i * kWgPitch + k0);
+      C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, C, 0, 0, 0);
     }
     __syncthreads();
   }
-  float* dst = a.dw + ((int64_t)t * a.c_in + c0 + 2 * ty) * a.c_out + o0 + 2 * tx;
-  atomicAdd(dst, acc[0][0]);
-  atomicAdd(dst + 1, acc[0][1]);
-  atomicAdd(dst + a.c_out, acc[1][0]);
-  atomicAdd(dst + a.c_out + 1, acc[1][1]);
+  // C[v] holds (c = 8 (v / 4) + 4 half + v % 4, o = i); the waves' tiles meet in LDS
+  // (16 KiB in xt, free since the last barrier)
+  float* red = reinterpret_cast<float*>(xt);         // [4 waves][32 c][32 o]
+#pragma unroll
+  for (int v = 0; v < 16; ++v) red[(wv * 32 + 8 * (v >> 2) + 4 * half + (v & 3)) * 32 + i] = C[v];
+  __syncthreads();
+  for (int e = tid; e < 1024; e += 256) {
+    const float sum = red[e] + red[1024 + e] + red[2048 + e] + red[3072 + e];
+    atomicAdd(a.dw + ((int64_t)t * a.c_in + c0 + (e >> 5)) * a.c_out + o0 + (e & 31), sum);
+  }
 }
 
 // column sums of dy over pixels: one workgroup per (channel tile of 64, pixel chunk)
@@ -802,11 +821,11 @@ pam_status_t pam_nn_conv3x3(const void* x, int32_t ldx, int32_t batch, int32_t h
 pam_status_t pam_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_t lddy, int32_t batch, int32_t h,
                                   int32_t w, int32_t c_in, int32_t c_out, float* dw, float* db, void* hip_stream) {
   if (!x || !dy || !dw || batch < 1 || h < 1 || w < 1 || c_in < 32 || c_in % 32 || c_out < 32 || c_out % 32 ||
-      ldx < c_in || lddy < c_out)
+      ldx < c_in || ldx % 8 || lddy < c_out || lddy % 8 || !aligned16(x) || !aligned16(dy))
     return PAM_ERR_INVALID_ARG;
   const int64_t P = (int64_t)batch * h * w;
   const int64_t n_chunks = std::max<int64_t>(1, std::min<int64_t>(64, P / 4096));
-  const int64_t chunk = ((P + n_chunks - 1) / n_chunks + 63) / 64 * 64;
+  const int64_t chunk = ((P + n_chunks - 1) / n_chunks + kWgSlab - 1) / kWgSlab * kWgSlab;
   WgradArgs a{static_cast<const bf16*>(x), static_cast<const bf16*>(dy), dw, P, chunk, ldx, lddy, h, w, c_in, c_out};
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   hipLaunchKernelGGL(wgrad_kernel, dim3(c_in / 32, c_out / 32, 9 * blocks_for(P, (int)chunk)), dim3(256), 0, st, a);

@@ -283,6 +283,40 @@ def test_conv3x3_against_reference(env, h, w, k_in, n_out, ldx_pad, mode):
     assert rel(got, want) < 2 ** -8
 
 
+@pytest.mark.parametrize("B,h,w,c_in,c_out,ld_pad", [
+    (2, 13, 40, 64, 32, 32),     # 1040 pixels: one chunk, a ragged last slab, channel stride > c_in
+    (4, 32, 80, 32, 96, 0),      # 10240 pixels: two chunks of 20 slabs, three output-channel tiles
+])
+def test_conv3x3_wgrad_against_reference(env, B, h, w, c_in, c_out, ld_pad):
+    """Weight and bias gradients of one convolution on BF16 operands against the FP64 reference of
+    the same BF16 values: the products are exact in FP32, so only the FP32 accumulation order
+    differs (relative error a few 1e-7 here)."""
+    torch, nn, S = env
+    rng = np.random.default_rng(B * h * w + c_in + c_out)
+    x = bf16_round(rng.standard_normal((B, h, w, c_in)))
+    dy = bf16_round(rng.standard_normal((B, h, w, c_out)))
+    xd = torch.zeros((B, h, w, c_in + ld_pad), dtype=torch.bfloat16, device="cuda")
+    xd[..., :c_in] = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16)
+    dyd = torch.zeros((B, h, w, c_out + ld_pad), dtype=torch.bfloat16, device="cuda")
+    dyd[..., :c_out] = torch.tensor(dy, dtype=torch.float32).to(torch.bfloat16)
+    dw = torch.zeros((9, c_in, c_out), dtype=torch.float32, device="cuda")
+    db = torch.zeros(c_out, dtype=torch.float32, device="cuda")
+    nn.conv3x3_wgrad(xd, c_in + ld_pad, dyd, c_out + ld_pad, B, h, w, c_in, c_out, dw, db)
+    torch.cuda.synchronize()
+    W0 = np.zeros((9, c_in, c_out))
+    want_w, want_b = np.zeros_like(W0), np.zeros(c_out)
+    for b in range(B):
+        _, gw, gb = U.conv3x3_backward(x[b], W0, dy[b])
+        want_w += gw
+        want_b += gb
+    got_w, got_b = dw.cpu().numpy().astype(np.float64), db.cpu().numpy().astype(np.float64)
+    err = np.abs(got_w - want_w).max() / np.abs(want_w).max()
+    print(f"dW: max err / max |dW| = {err:.2e}, rel L2 {rel(got_w, want_w):.2e}; db rel L2 {rel(got_b, want_b):.2e}",
+          flush=True)
+    assert err < 1e-5 and rel(got_w, want_w) < 1e-6
+    assert rel(got_b, want_b) < 1e-6
+
+
 def test_shipped_calibration_on_benchmark_frames(env):
     """The shipped weights on fresh benchmark-geometry frames (seeds outside every training,
     calibration and evaluation set): fallback frames are plain AS-TAX exactly, and frames
