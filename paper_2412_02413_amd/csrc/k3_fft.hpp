@@ -316,7 +316,10 @@ __global__ __launch_bounds__(256, 2) void k3fft(K3Args a0, K3Groups grp) {
     for (int i = 0; i < NSUB; ++i) {
       idft16(p[i]);                                                // Y(x1, q2 = j), x1 = 0..15
 #pragma unroll
-      for (int x1 = 0; x1 < 16; ++x1) tr[x1 * kFfRow + j] = cmul(p[i][x1], twl[x1 * 16 + j]);
+      for (int x1 = 0; x1 < 16; ++x1)   // (the twiddle of x1 = 0 is exactly 1; skipped at N = 512 only,
+                                        // where it shortens the spill, 76 -> 20 bytes a lane; at N = 128
+                                        // and 256 the compiler's allocation then spills)
+        tr[x1 * kFfRow + j] = (R == 2 && x1 == 0) ? p[i][0] : cmul(p[i][x1], twl[x1 * 16 + j]);
       __builtin_amdgcn_wave_barrier();
       const float4* yr = reinterpret_cast<const float4*>(tr + j * kFfRow);   // row x1 = j
 #pragma unroll
