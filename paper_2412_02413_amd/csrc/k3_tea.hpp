@@ -68,7 +68,7 @@ __global__ __launch_bounds__(TEA_THREADS) void k3_tea(TeaArgs a) {
     __syncthreads();
     const float2* src = a.spectra + ((size_t)f * a.n_sel + b0) * a.L;
     for (int e = threadIdx.x; e < nb * a.L; e += TEA_THREADS) xs[e] = src[e];
-    if (threadIdx.x < nb) ks[threadIdx.x] = a.ksel[b0 + threadIdx.x];
+    if ((int)threadIdx.x < nb) ks[threadIdx.x] = a.ksel[b0 + threadIdx.x];
     __syncthreads();
     float2 p[NSUB][TEA_BC];
 #pragma unroll

@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void k2_lateral(K2Args a) {
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
     __syncthreads();
   }
   const float gmax = red[0];
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(256) void k4_weight(K4Args a) {
   red[threadIdx.x] = wv;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
     __syncthreads();
   }
   if (threadIdx.x == 0) a.blockmax[(size_t)f * a.n_blk + blockIdx.x] = red[0];
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(256) void k4_image(K4Args a) {
   red[threadIdx.x] = m;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
     __syncthreads();
   }
   const float mx = red[0];

@@ -87,7 +87,6 @@ float from_fp16(uint16_t u) {
 }
 bool is_split(int prec) { return prec != PAM_PREC_FP32; }
 bool is_fp16(int prec) { return prec == PAM_PREC_SPLIT_FP16 || prec == PAM_PREC_FP16; }
-int passes(int prec) { return (prec == PAM_PREC_SPLIT_BF16 || prec == PAM_PREC_SPLIT_FP16) ? 3 : 1; }
 
 }  // namespace
 

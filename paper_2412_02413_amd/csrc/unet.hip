@@ -13,7 +13,6 @@ typedef __bf16 bf16;
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-inline bool ok_stream(hipError_t e) { return e == hipSuccess; }
 inline pam_status_t launched() { return hipGetLastError() == hipSuccess ? PAM_OK : PAM_ERR_DEVICE; }
 
 // ---------------------------------------------------------------------------
@@ -515,7 +514,7 @@ __global__ __launch_bounds__(256) void head_kernel(const bf16* feat, int32_t c, 
   red[2][threadIdx.x] = l2;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
       red[0][threadIdx.x] += red[0][threadIdx.x + s];
       red[1][threadIdx.x] += red[1][threadIdx.x + s];
       red[2][threadIdx.x] += red[2][threadIdx.x + s];
@@ -539,7 +538,7 @@ __global__ __launch_bounds__(1024) void loss_weights_kernel(const float* E, int6
   red[threadIdx.x] = s;
   __syncthreads();
   for (int k = 512; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
   const float inv = red[0] > 0.f ? (1.f - mix) / red[0] : 0.f;
@@ -607,7 +606,7 @@ __global__ __launch_bounds__(1024) void features_kernel(const float* E, int64_t 
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
   const float mx = red[0] > 0.f ? red[0] : 1.f;
@@ -661,7 +660,7 @@ __global__ __launch_bounds__(256) void energy_max_kernel(const float* acc, int32
   red[threadIdx.x] = v;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0) atomicMax(fmax + f, __float_as_uint(red[0]));
@@ -734,7 +733,7 @@ __global__ __launch_bounds__(1024) void error_estimate_kernel(const float* mask,
   s1[threadIdx.x] = b;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
       s0[threadIdx.x] += s0[threadIdx.x + s];
       s1[threadIdx.x] += s1[threadIdx.x + s];
     }
@@ -757,7 +756,7 @@ __global__ __launch_bounds__(1024) void confidence_kernel(const float* err, cons
   s1[threadIdx.x] = b;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
       s0[threadIdx.x] += s0[threadIdx.x + s];
       s1[threadIdx.x] += s1[threadIdx.x + s];
     }
