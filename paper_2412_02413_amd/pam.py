@@ -208,6 +208,8 @@ def pam_as_tax_grouped(plan: Plan, rf, groups, image, nncc=None, rho_pairs=None,
     def bad(msg):
         raise PamError(-1, f"pam_as_tax_grouped: {msg}")
 
+    if not groups or any(int(f) < 0 for _, f in groups):
+        bad("groups must be a non-empty list of (n_t, n_frames >= 0)")
     for name, t, count in (("rf", rf, want_rf), ("image", image, F * info.n_z * info.n_x),
                            ("nncc", nncc, F * info.n_z * info.n_x),
                            ("rho_pairs", rho_pairs, F * info.n_pairs * info.n_z * info.n_x)):
@@ -215,10 +217,14 @@ def pam_as_tax_grouped(plan: Plan, rf, groups, image, nncc=None, rho_pairs=None,
             if name in ("rf", "image"):
                 bad(f"{name} is required")
             continue
-        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
-            bad(f"{name} must be a contiguous float32 device tensor")
+        if not (t.dtype == torch.float32 and t.is_contiguous()):
+            bad(f"{name} must be a contiguous float32 tensor")
         if t.numel() != count:
             bad(f"{name} holds {t.numel()} values, expected {count}")
+    for name, t in (("rf", rf), ("image", image), ("nncc", nncc), ("rho_pairs", rho_pairs),
+                    ("workspace", workspace)):
+        if t is not None and (t.device.type != "cuda" or t.device.index != info.device):
+            bad(f"{name} must live on cuda:{info.device}, got {t.device}")
     stream = stream or torch.cuda.current_stream()
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(_lib().pam_as_tax_grouped(C.c_void_p(plan.handle), _ptr(rf), _groups(groups), len(groups), _ptr(image),

@@ -86,6 +86,29 @@ def test_valid_geometry_without_gpu_reports_device_error():
     assert plan_status(synth.cfg1_geometry()) == P.PAM_ERR_DEVICE
 
 
+def test_grouped_binding_checks_on_cpu():
+    """pam_as_tax_grouped rejects, before any library call, an empty group list, a packed RF
+    of the wrong size, a short image, a non-float32 buffer and (here) host tensors."""
+    import torch
+    info = P.PlanInfoC(n_bins=1639, n_z=151, n_x=128, n_sub=3, n_elements=64, n_samples=8192, n_pairs=3,
+                       device=0)
+    plan = P.Plan(0, None, "fp32", info)
+    groups = [(2048, 2), (4096, 1)]
+    rf = torch.zeros(64 * (2 * 2048 + 4096))
+    img = torch.zeros((3, 151, 128))
+    cases = [
+        ([], rf, img),
+        (groups, torch.zeros(64 * (2 * 2048 + 4096) - 1), img),
+        (groups, rf, torch.zeros((2, 151, 128))),
+        (groups, rf.double(), img),
+        (groups, rf, img),                                   # right sizes, but not on the GPU
+    ]
+    for g, r, i in cases:
+        with pytest.raises(P.PamError) as ei:
+            P.pam_as_tax_grouped(plan, r, g, i)
+        assert ei.value.status == P.PAM_ERR_INVALID_ARG
+
+
 def test_binding_buffer_checks_on_cpu():
     """check_buffers rejects a wrong channel count, a short image, a non-float32 RF, a
     non-contiguous view and (here) host tensors, each before any library call."""
