@@ -154,7 +154,8 @@ def test_grouped_call_mixes_record_lengths(env, precision):
 def test_grouped_work_list_launch(env, precision):
     """One frame of each record length on a shallow grid (33 depths: two depth tiles a frame
     at 128 columns in FP32): no length fills the device alone, so the fields stage runs as ONE
-    grouped work-list launch (FP32; the split form at 128 columns runs per length).  Every
+    grouped work-list launch (FP32; the split form at 128 columns runs per length).  An empty
+    group sits between the first two, so the work list also skips a zero-frame group.  Every
     frame equals its per-length call up to summation order and the FP64 oracle at the form's
     tolerance."""
     torch, pam = env
@@ -163,7 +164,7 @@ def test_grouped_work_list_launch(env, precision):
     em = [synth.Emitter(1 * MM, 30 * MM, "broadband"), synth.Emitter(-4 * MM, 26 * MM, "stable")]
     lengths = [2048, 4096, 8192]
     frames = {n: synth.render(g, em, rng, n_t=n)[None] for n in lengths}
-    groups = [(n, 1) for n in lengths]
+    groups = [(lengths[0], 1), (lengths[1], 0)] + [(n, 1) for n in lengths[1:]]
     plan = pam.pam_plan(g, 0, precision)
     try:
         assert pam.debug_grouped_one_launch(plan, groups) == (precision == "fp32")
