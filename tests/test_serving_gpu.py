@@ -41,6 +41,29 @@ def test_mix_equals_alone(env):
         srv.close()
 
 
+def test_largest_frame_in_the_mix_equals_alone(env):
+    """The largest serving frame, a 256-element array on 512 columns with 16,384 samples at
+    40 MHz, served in a mix with small 64-element requests: each of its images equals the same
+    request run alone (relative L2 1e-5; only the bin split of the batch changes the FP32
+    summation order)."""
+    torch, pam, serving, _ = env
+    pool = serving.make_pool(seed=11, arrays=(64, 256), rates=(40e6,), lengths=(1024, 16384))
+    srv = serving.Server(max_batch=4, n_streams=3, max_samples=16384)
+    try:
+        reqs = serving.poisson_requests(pool, 5000.0, 16, seed=7)
+        big = [r for r in reqs if r.key.n_elements == 256 and r.n_t == 16384]
+        assert big, "the request mix holds no 256-element, 16,384-sample frame"
+        srv.run(reqs)
+        assert all(r.status == "done" for r in reqs)
+        for r in big[:3]:
+            ref = alone(pam, torch, srv, r)
+            e = float(np.linalg.norm(r.image - ref) / np.linalg.norm(ref))
+            print(f"request {r.rid}: 256 elements, 16384 samples, mixed vs alone relL2 {e:.2e}", flush=True)
+            assert e <= 1e-5, (r.rid, e)
+    finally:
+        srv.close()
+
+
 def test_budget_admission_and_rejection(env):
     torch, pam, serving, pool = env
     probe = serving.Server(max_samples=2048)
