@@ -13,7 +13,7 @@ threshold falls back to plain AS-TAX.  The threshold is calibrated on held-out
 frames of that geometry (split conformal on the ratio of true to predicted
 error) so that an accepted frame exceeds a stated image-error bound with
 probability at most alpha.  Plain AS-TAX on the GPU generates the training
-targets and judges the result.
+targets and is the reference the surrogate's images are scored against.
 
 Every numerical step runs in the HIP library: the reconstructions through
 pam_as_tax, the network through the pam_nn_* kernels.  This module owns the
