@@ -650,7 +650,7 @@ def main():
         for k in range(args.steps):
             for i, s in enumerate(pam.STAGES):
                 stage_ms[s] += ev.elapsed_ms(events[k][i], events[k][i + 1]) / args.steps
-        lat_gpu, lat_wall = [], []
+        lat_gpu, lat_wall, lat_graph = [], [], []
         if latency_calls > 0:
             img1 = torch.empty((1, geom.n_z, geom.n_x), device=dev)
             ws1 = pam.alloc_workspace(plan, 1, geom.n_samples, dev)
@@ -664,12 +664,38 @@ def main():
                 if c >= 3:
                     lat_wall.append(1e3 * (time.perf_counter() - tw))
                     lat_gpu.append(ev.elapsed_ms(e1[0], e1[-1]))
+            # the same single-frame call replayed from a graph captured once on a side stream
+            # (the library's launches only; each frame is copied into the captured input first,
+            # outside the timed region)
+            gs = torch.cuda.Stream(device=dev)
+            x1 = rf[0:1].clone()
+            img_g = torch.empty_like(img1)
+            ws_g = pam.alloc_workspace(plan, 1, geom.n_samples, dev)
+            with torch.cuda.stream(gs):
+                pam.pam_as_tax(plan, x1, img_g, None, None, ws_g, gs)
+            gs.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=gs):
+                pam.pam_as_tax(plan, x1, img_g, None, None, ws_g, gs)
+            torch.cuda.synchronize()
+            for c in range(latency_calls + 3):
+                x1.copy_(rf[c % F: c % F + 1])
+                torch.cuda.synchronize()
+                g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                with torch.cuda.stream(gs):
+                    g0.record(gs)
+                    graph.replay()
+                    g1.record(gs)
+                g1.synchronize()
+                if c >= 3:
+                    lat_graph.append(g0.elapsed_time(g1))
+            del graph
         n_sel = plan.info.n_bins
         lay = pam.pam_workspace_layout(plan, F, geom.n_samples)
         pam.pam_destroy(plan)
         res = {"precision": precision, "ms_per_step": 1e3 * wall / args.steps,
                "frames_per_s": F * args.steps / wall, "stage_ms": stage_ms, "n_sel": n_sel,
-               "lat_gpu": lat_gpu, "lat_wall": lat_wall, "layout": lay, "images": image,
+               "lat_gpu": lat_gpu, "lat_wall": lat_wall, "lat_graph": lat_graph, "layout": lay, "images": image,
                "acc_images": image[:n_acc].cpu().numpy().astype(np.float64),
                "acc_nncc": nncc[:n_acc].cpu().numpy().astype(np.float64)}
         log(f"{precision}: {res['ms_per_step']:.2f} ms/step, {res['frames_per_s']:.1f} frames/s, "
@@ -701,7 +727,9 @@ def main():
                                          main_res["stage_ms"], main_res["n_sel"])
     lat_gpu, lat_wall = main_res["lat_gpu"], main_res["lat_wall"]
     if lat_gpu:
-        log(f"latency: p50 {np.percentile(lat_gpu, 50):.3f} ms p99 {np.percentile(lat_gpu, 99):.3f} ms (GPU)")
+        log(f"latency: p50 {np.percentile(lat_gpu, 50):.3f} ms p99 {np.percentile(lat_gpu, 99):.3f} ms (GPU); "
+            f"graph replay p50 {np.percentile(main_res['lat_graph'], 50):.3f} p99 "
+            f"{np.percentile(main_res['lat_graph'], 99):.3f} ms")
     roof = fields_roofline(main_res, args.precision)
     roof["traffic"] = recorded_traffic(args.precision)
     roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(main_res["layout"], F, n_sel, geom)
@@ -811,6 +839,8 @@ def main():
         "latency_ms_per_frame": ({"p50": round(float(np.percentile(lat_gpu, 50)), 4),
                                   "p99": round(float(np.percentile(lat_gpu, 99)), 4),
                                   "p99_host_wall": round(float(np.percentile(lat_wall, 99)), 4),
+                                  "graph_p50": round(float(np.percentile(main_res["lat_graph"], 50)), 4),
+                                  "graph_p99": round(float(np.percentile(main_res["lat_graph"], 99)), 4),
                                   "calls": len(lat_gpu), "frames_per_call": 1} if lat_gpu else None),
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_rooflines": stages_roof,

@@ -362,6 +362,45 @@ def test_largest_serving_frame(pam, torch_cuda, precision):
     check_end_to_end(res, ref, tol_i=tol_i, tol_rho=tol_rho)
 
 
+def test_graph_replay_matches_eager(pam, torch_cuda):
+    """pam_as_tax captured once into a HIP graph (its launches only: the call allocates and
+    clears nothing) and replayed four times, each time on new frames copied into the captured
+    input, with eager work and synchronisations between the replays: every replay equals the
+    eager call on the same frames bit for bit."""
+    torch = torch_cuda
+    g = synth.cfg1_geometry()
+    frames = synth.batch(synth.cfg1_frame, [11, 12, 13, 14, 15, 16, 17, 18])
+    plan = pam.pam_plan(g, 0, "fp32")
+    try:
+        x = torch.from_numpy(frames[:2]).cuda()
+        img, nn = torch.empty((2, g.n_z, g.n_x), device="cuda"), torch.empty((2, g.n_z, g.n_x), device="cuda")
+        ws = pam.alloc_workspace(plan, 2, g.n_samples)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            pam.pam_as_tax(plan, x, img, nn, None, ws, s)
+        s.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            pam.pam_as_tax(plan, x, img, nn, None, ws, s)
+        torch.cuda.synchronize()
+        for k in range(4):
+            x.copy_(torch.from_numpy(frames[2 * k:2 * k + 2]))
+            img.zero_()
+            nn.zero_()
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            got_i, got_n = img.clone(), nn.clone()
+            # the eager call on the same frames, with its own buffers
+            img_e, nn_e = torch.empty_like(img), torch.empty_like(nn)
+            pam.pam_as_tax(plan, x, img_e, nn_e, None, pam.alloc_workspace(plan, 2, g.n_samples))
+            torch.cuda.synchronize()
+            assert torch.equal(got_i, img_e) and torch.equal(got_n, nn_e), k
+        del graph
+    finally:
+        pam.pam_destroy(plan)
+
+
 @pytest.mark.parametrize("n_t,L", [(32, 8), (256, 8), (256, 7), (2048, 6), (4096, 8), (4096, 9), (16384, 8)])
 def test_stage_time_fft_record_lengths(pam, torch_cuda, n_t, L):
     """K1 (the time FFT) on every pass structure it runs: 32 samples (radix 8 then 2),
